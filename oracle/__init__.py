@@ -1,0 +1,329 @@
+"""Plain FP64 CPU oracle for the lookback intensity sum -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never links, loads
+or calls it, and it shares no code with the HIP path.
+
+Contents
+--------
+* ``render`` / ``render_brute``: O1 (sorted plane crossings) and O2 (every cell
+  box tested) from ``dart_oracle.c``; both evaluate the discrete sum of Eq. 19
+  (paper Sec. 2.5) with the chord midpoint as the sampling point of the retarded
+  time (Eq. 2) and the linear epoch weights of Eqs. 6-7.
+* ``quadrature``: O3, a numpy fine-step quadrature of the continuous integral
+  of Eq. 18 over the same piecewise-constant-in-space, piecewise-linear-in-time
+  field.  It takes no step of O1 and serves as an independent check.
+* closed forms from the paper's Sec. 3: Doppler factor (Eq. 14), apparent
+  transverse speed (Eq. 21), flux laws and flux ratio (Eqs. 22-23), aliasing
+  cadence (Eqs. 24-25).
+
+Conventions (the readings are listed in the design doc): alpha is the positive index
+of S ~ nu^-alpha, so the per-cell exponent is p = 2 + alpha (the paper's
+2 - alpha with its alpha = -0.6 default); c = 1; theta is the polar angle of the
+direction to the observer from +z and phi its azimuth from +x, in degrees.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dart_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+
+NO_LOOKBACK = 1
+NO_BEAMING = 2
+NEAREST = 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc -O2 (no fast-math) into ``oracle/liborc.so``."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("cell", ctypes.c_double * 3),
+                ("n_epochs", ctypes.c_int), ("times", ctypes.POINTER(ctypes.c_double)),
+                ("dtype", ctypes.c_int), ("j", ctypes.c_void_p), ("beta", ctypes.c_void_p)]
+
+
+class _View(ctypes.Structure):
+    _fields_ = [("theta_deg", ctypes.c_double), ("phi_deg", ctypes.c_double),
+                ("width", ctypes.c_int), ("height", ctypes.c_int),
+                ("pixel_scale", ctypes.c_double), ("t_obs", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("flags", ctypes.c_uint)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        for name in ("orc_render", "orc_render_brute"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View), ctypes.c_void_p,
+                          ctypes.c_longlong, ctypes.c_void_p,
+                          ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
+        lib.orc_epoch_weights.restype = ctypes.c_int
+        lib.orc_epoch_weights.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_uint,
+                                          ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_double)]
+        lib.orc_segments.restype = ctypes.c_int
+        lib.orc_segments.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View), ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
+        lib.orc_count_samples.restype = ctypes.c_longlong
+        lib.orc_count_samples.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View)]
+        lib.orc_camera_basis.restype = None
+        lib.orc_camera_basis.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View),
+                                         ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Stack:
+    """Epoch stack in the caller's layout: j [M][nz][ny][nx], beta [M][nz][ny][nx][3]."""
+    j: np.ndarray
+    beta: np.ndarray
+    times: np.ndarray
+    cell: tuple = (1.0, 1.0, 1.0)
+
+    def __post_init__(self):
+        dt = np.float32 if self.j.dtype == np.float32 else np.float64
+        self.j = np.ascontiguousarray(self.j, dtype=dt)
+        self.beta = np.ascontiguousarray(self.beta, dtype=dt)
+        self.times = np.ascontiguousarray(self.times, dtype=np.float64)
+        M, nz, ny, nx = self.j.shape
+        assert self.beta.shape == (M, nz, ny, nx, 3)
+        assert self.times.shape == (M,)
+
+    @property
+    def dims(self):
+        M, nz, ny, nx = self.j.shape
+        return (nx, ny, nz)
+
+    def _cgrid(self) -> _Grid:
+        g = _Grid()
+        nx, ny, nz = self.dims
+        g.n[:] = [nx, ny, nz]
+        g.cell[:] = [float(c) for c in self.cell]
+        g.n_epochs = self.j.shape[0]
+        g.times = self.times.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g.dtype = 1 if self.j.dtype == np.float32 else 0
+        g.j = self.j.ctypes.data
+        g.beta = self.beta.ctypes.data
+        return g
+
+
+@dataclass
+class View:
+    theta_deg: float
+    phi_deg: float
+    width: int
+    height: int
+    pixel_scale: float
+    t_obs: float
+    alpha: float
+    flags: int = 0
+
+    def _cview(self) -> _View:
+        return _View(float(self.theta_deg), float(self.phi_deg), int(self.width),
+                     int(self.height), float(self.pixel_scale), float(self.t_obs),
+                     float(self.alpha), int(self.flags))
+
+
+def _threads(n):
+    if n is None:
+        n = int(os.environ.get("ORACLE_THREADS", "0")) or (os.cpu_count() or 1)
+    return max(1, int(n))
+
+
+def _run(fn, stack: Stack, view: View, pixels=None, threads=None):
+    lib = _load()
+    g = stack._cgrid()
+    v = view._cview()
+    if pixels is None:
+        out = np.zeros((view.height, view.width), dtype=np.float64)
+        pix_ptr, n = None, view.width * view.height
+    else:
+        pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int32).reshape(-1, 2))
+        out = np.zeros(pix.shape[0], dtype=np.float64)
+        pix_ptr, n = pix.ctypes.data, pix.shape[0]
+    steps = ctypes.c_longlong(0)
+    rc = getattr(lib, fn)(ctypes.byref(g), ctypes.byref(v), pix_ptr, n, out.ctypes.data,
+                          ctypes.byref(steps), _threads(threads))
+    if rc != 0:
+        raise ValueError(f"oracle {fn} rejected its arguments (rc={rc})")
+    return out, int(steps.value)
+
+
+def render(stack: Stack, view: View, pixels=None, threads=None):
+    """O1.  Returns (intensity, cell_steps).  ``pixels`` is an (n, 2) array of
+    (i, j) pixel indices; without it the whole [height][width] image is made."""
+    return _run("orc_render", stack, view, pixels, threads)
+
+
+def render_brute(stack: Stack, view: View, pixels=None, threads=None):
+    """O2: per-cell box test against every cell (tiny grids only)."""
+    return _run("orc_render_brute", stack, view, pixels, threads)
+
+
+def flux(image: np.ndarray, view: View) -> float:
+    """Total flux: sum of pixel intensities times the pixel area (Eq. 22 up to
+    the constant 1/L^2)."""
+    return float(np.sum(image, dtype=np.float64) * view.pixel_scale ** 2)
+
+
+def epoch_weights(times, tbar, flags=0):
+    """Eqs. 6-7: list of (epoch, weight) pairs; empty outside the window."""
+    lib = _load()
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    ms = (ctypes.c_int * 2)()
+    ws = (ctypes.c_double * 2)()
+    k = lib.orc_epoch_weights(t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(t),
+                              float(tbar), int(flags), ms, ws)
+    return [(ms[q], ws[q]) for q in range(k)]
+
+
+def segments(stack: Stack, view: View, i: int, j: int):
+    """O1's chords for pixel (i, j): array of (s_a, s_b, linear cell index)."""
+    lib = _load()
+    nx, ny, nz = stack.dims
+    cap = 2 + nx + ny + nz
+    out = np.zeros((cap, 3), dtype=np.float64)
+    k = lib.orc_segments(ctypes.byref(stack._cgrid()), ctypes.byref(view._cview()), i, j,
+                         out.ctypes.data, cap)
+    return out[:k].copy()
+
+
+def count_samples(stack: Stack, view: View) -> int:
+    """Distinct (cell, epoch) samples with positive weight over the image."""
+    lib = _load()
+    return int(lib.orc_count_samples(ctypes.byref(stack._cgrid()), ctypes.byref(view._cview())))
+
+
+def camera_basis(stack: Stack, view: View):
+    """(s_hat, e_u, e_v, centre) as the oracle builds them."""
+    lib = _load()
+    out = np.zeros(12, dtype=np.float64)
+    lib.orc_camera_basis(ctypes.byref(stack._cgrid()), ctypes.byref(view._cview()),
+                         out.ctypes.data)
+    return out[0:3], out[3:6], out[6:9], out[9:12]
+
+
+# --------------------------------------------------------------------------
+# O3: fine-step quadrature of the continuous integral (Eq. 18), no chords
+# --------------------------------------------------------------------------
+
+def quadrature(stack: Stack, view: View, i: int, j: int, h: float = 1e-3):
+    """Midpoint-rule quadrature along pixel (i, j)'s ray with step h (in length
+    units): at each sample point the cell is looked up, the retarded time is
+    t_obs - s (Eq. 2), the epoch pair is interpolated linearly in time (Eq. 7)
+    and D^p j is summed.  Cells outside the window contribute nothing, sample by
+    sample (not cell by cell)."""
+    nx, ny, nz = stack.dims
+    dims = np.array([nx, ny, nz])
+    cell = np.array(stack.cell, dtype=np.float64)
+    st, ct, sp, cp = _sc(view.theta_deg) + _sc(view.phi_deg)
+    shat = -np.array([st * cp, st * sp, ct])
+    eu = np.array([-sp, cp, 0.0])
+    ev = np.array([-ct * cp, -ct * sp, st])
+    centre = 0.5 * dims * cell
+    u = (i + 0.5 - 0.5 * view.width) * view.pixel_scale
+    v = (j + 0.5 - 0.5 * view.height) * view.pixel_scale
+    o = centre + u * eu + v * ev
+    half = 0.5 * float(np.linalg.norm(dims * cell)) + 1.0
+    n = int(math.ceil(2 * half / h))
+    s = -half + (np.arange(n) + 0.5) * (2 * half / n)
+    step = 2 * half / n
+    x = o[None, :] + s[:, None] * shat[None, :]
+    idx = np.floor(x / cell).astype(np.int64)
+    ok = np.all((idx >= 0) & (idx < dims), axis=1)
+    s, idx = s[ok], idx[ok]
+    tbar = np.full_like(s, view.t_obs) if view.flags & NO_LOOKBACK else view.t_obs - s
+    t = stack.times
+    M = len(t)
+    inwin = (tbar >= t[0]) & (tbar <= t[-1])
+    s, idx, tbar = s[inwin], idx[inwin], tbar[inwin]
+    lin = (idx[:, 2] * ny + idx[:, 1]) * nx + idx[:, 0]
+    jf = stack.j.reshape(M, -1).astype(np.float64)
+    bf = stack.beta.reshape(M, -1, 3).astype(np.float64)
+    p = 2.0 + view.alpha
+
+    def boosted(m):
+        jv = jf[m, lin]
+        if view.flags & NO_BEAMING:
+            return jv
+        b = bf[m, lin]
+        D = np.sqrt(1.0 - np.sum(b * b, axis=1)) / (1.0 + b @ shat)
+        return D ** p * jv
+
+    if M == 1:
+        return float(np.sum(boosted(np.zeros(len(lin), dtype=np.int64))) * step)
+    m = np.clip(np.searchsorted(t, tbar, side="right") - 1, 0, M - 2)
+    w = (tbar - t[m]) / (t[m + 1] - t[m])
+    if view.flags & NEAREST:
+        take = np.where((t[m + 1] - tbar) < (tbar - t[m]), m + 1, m)
+        return float(np.sum(boosted(take)) * step)
+    val = (1.0 - w) * boosted(m) + w * boosted(m + 1)
+    return float(np.sum(val) * step)
+
+
+def _sc(deg):
+    r = math.fmod(deg, 360.0)
+    if r < 0:
+        r += 360.0
+    exact = {0.0: (0.0, 1.0), 90.0: (1.0, 0.0), 180.0: (0.0, -1.0), 270.0: (-1.0, 0.0)}
+    if r in exact:
+        return exact[r]
+    return (math.sin(math.radians(deg)), math.cos(math.radians(deg)))
+
+
+# --------------------------------------------------------------------------
+# Closed forms from the paper's Sec. 3 and Sec. 6.1
+# --------------------------------------------------------------------------
+
+def lorentz(beta: float) -> float:
+    return 1.0 / math.sqrt(1.0 - beta * beta)
+
+
+def doppler(beta_vec, shat) -> float:
+    """Eq. 14: D = 1 / (Gamma (1 + beta . s_hat))."""
+    b = np.asarray(beta_vec, dtype=np.float64)
+    return float(math.sqrt(1.0 - b @ b) / (1.0 + b @ np.asarray(shat, dtype=np.float64)))
+
+
+def apparent_speed(beta: float, theta_rad: float) -> float:
+    """Eq. 21: beta_T = beta sin(theta) / (1 - beta cos(theta))."""
+    return beta * math.sin(theta_rad) / (1.0 - beta * math.cos(theta_rad))
+
+
+def flux_ratio(beta: float, theta_rad: float, exponent: float) -> float:
+    """Eq. 23 with a general exponent: ((1 + b cos th) / (1 - b cos th))^exponent."""
+    return ((1.0 + beta * math.cos(theta_rad)) / (1.0 - beta * math.cos(theta_rad))) ** exponent
+
+
+def alias_dt_crit(beta: float, theta_rad: float, radius: float) -> float:
+    """Eq. 24: the largest snapshot cadence that resolves a region of size R."""
+    return (1.0 - beta * math.cos(theta_rad)) / math.sin(theta_rad) * radius / beta
+
+
+def alias_r_crit(beta: float, theta_rad: float, dt: float) -> float:
+    """Eq. 25: the smallest resolved length scale at cadence dt."""
+    return beta * math.sin(theta_rad) * dt / (1.0 - beta * math.cos(theta_rad))

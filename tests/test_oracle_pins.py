@@ -1,0 +1,548 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle (O1: sorted plane crossings; O2: every cell box
+tested; O3: fine-step quadrature) against a value that does not come from the
+oracle itself: closed forms, brute force, the paper's worked example, exact
+symmetries.  No GPU is involved.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _stack(orc, j, beta, times, cell=(1.0, 1.0, 1.0)):
+    return orc.Stack(j=j, beta=beta, times=np.asarray(times, dtype=np.float64), cell=cell)
+
+
+def _box_chord(o, d, lo, hi):
+    """Independent slab test (numpy) for the chord of ray o + s d in [lo, hi)."""
+    a, b = -np.inf, np.inf
+    for k in range(3):
+        if d[k] == 0.0:
+            if not (lo[k] <= o[k] < hi[k]):
+                return 0.0
+            continue
+        t0, t1 = (lo[k] - o[k]) / d[k], (hi[k] - o[k]) / d[k]
+        a, b = max(a, min(t0, t1)), min(b, max(t0, t1))
+    return max(0.0, b - a)
+
+
+def _ray(view, dims, cell, i, j):
+    """Pixel ray built from the camera convention stated in the oracle header."""
+    st, ct = math.sin(math.radians(view.theta_deg)), math.cos(math.radians(view.theta_deg))
+    sp, cp = math.sin(math.radians(view.phi_deg)), math.cos(math.radians(view.phi_deg))
+    n = np.array([st * cp, st * sp, ct])
+    eu = np.array([-sp, cp, 0.0])
+    ev = np.array([-ct * cp, -ct * sp, st])
+    C = 0.5 * np.asarray(dims, float) * np.asarray(cell, float)
+    u = (i + 0.5 - view.width / 2) * view.pixel_scale
+    v = (j + 0.5 - view.height / 2) * view.pixel_scale
+    return C + u * eu + v * ev, -n
+
+
+# ---------------------------------------------------------------- P1 cardinal views
+
+@pytest.mark.parametrize("theta,phi,expect", [
+    (90.0, 0.0, lambda J: J.sum(axis=2)),                   # s_hat = -x: I[z][y]
+    (0.0, 0.0, lambda J: J.sum(axis=0)[:, ::-1].T),         # s_hat = -z: I[j][i] = sum_z J[z, i, nx-1-j]
+    (90.0, 90.0, lambda J: J.sum(axis=1)[:, ::-1]),         # s_hat = -y: I[z][nx-1-i]
+    (180.0, 0.0, lambda J: J.sum(axis=0).T),                # s_hat = +z: I[j][i] = sum_z J[z, i, j]
+])
+def test_p1_cardinal_column_sums(orc, theta, phi, expect):
+    """Along a cardinal axis the sum reduces to a column sum (paper Sec. 1,
+    Sec. 2.4): image = numpy sum of the emissivity along that axis."""
+    n = 12
+    rng = np.random.default_rng(11)
+    J = rng.uniform(0.0, 2.0, size=(n, n, n))
+    j = J[None]
+    beta = np.zeros((1, n, n, n, 3))
+    s = _stack(orc, j, beta, [0.0])
+    v = orc.View(theta, phi, n, n, 1.0, 0.0, 0.7, orc.NO_LOOKBACK | orc.NO_BEAMING)
+    img, steps = orc.render(s, v, threads=2)
+    np.testing.assert_allclose(img, expect(J), rtol=1e-13, atol=0)
+    assert steps == n ** 3
+
+
+def test_p1_anisotropic_cells(orc):
+    """Non-cubic cells: the column sum carries the cell length along the ray."""
+    nx, ny, nz = 6, 5, 4
+    cell = (0.5, 2.0, 1.25)
+    rng = np.random.default_rng(5)
+    J = rng.uniform(0.0, 1.0, size=(nz, ny, nx))
+    s = _stack(orc, J[None], np.zeros((1, nz, ny, nx, 3)), [0.0], cell=cell)
+    # s_hat = -y: columns along y, pixel (i, j) at x = C_x - u, z = C_z + v
+    v = orc.View(90.0, 90.0, nx, nz, 0.5, 0.0, 0.0, orc.NO_LOOKBACK | orc.NO_BEAMING)
+    # pixel scale 0.5 matches dx but not dz: compare at pixel centres directly
+    img, _ = orc.render(s, v, threads=1)
+    for jrow in range(nz):
+        for i in range(nx):
+            o, d = _ray(v, (nx, ny, nz), cell, i, jrow)
+            ix = int(math.floor(o[0] / cell[0]))
+            iz = int(math.floor(o[2] / cell[2]))
+            want = J[iz, :, ix].sum() * cell[1]
+            assert img[jrow, i] == pytest.approx(want, rel=1e-13)
+
+
+# ---------------------------------------------------------------- P2 weights (Fig. 2)
+
+def test_p2_fig2_weights(orc):
+    g = json.load(open(os.path.join(GOLDEN, "fig2_worked_example.json")))
+    dt = g["dt"]
+    times = np.arange(0, 40) * dt
+    for cell, rec in g["printed"].items():
+        w = orc.epoch_weights(times, rec["tbar"])
+        assert [m for m, _ in w] == rec["epochs"]
+        want = g["derived_weights_eq7"][cell]
+        for m, wt in w:
+            assert wt == pytest.approx(want[str(m)], abs=1e-14)
+        # Eq. 7 literally: W = 1 - |tbar - t_m| / dt on the two bracketing epochs
+        for m, wt in w:
+            assert wt == pytest.approx(1 - abs(rec["tbar"] - m * dt) / dt, abs=1e-14)
+
+
+def test_p2_weights_edges(orc):
+    t = [0.0, 1.0, 3.0]
+    assert orc.epoch_weights(t, -1e-12) == []
+    assert orc.epoch_weights(t, 3.0 + 1e-12) == []
+    assert orc.epoch_weights(t, 3.0) == [(1, 0.0), (2, 1.0)]
+    assert orc.epoch_weights(t, 0.0) == [(0, 1.0), (1, 0.0)]
+    assert orc.epoch_weights(t, 2.0) == [(1, 0.5), (2, 0.5)]
+    # nearest epoch: ties go to the earlier epoch
+    assert orc.epoch_weights(t, 2.0, orc.NEAREST) == [(1, 1.0)]
+    assert orc.epoch_weights(t, 2.0 + 1e-9, orc.NEAREST) == [(2, 1.0)]
+    assert orc.epoch_weights([5.0], 5.0) == [(0, 1.0)]
+    assert orc.epoch_weights([5.0], 5.0 + 1e-9) == []
+
+
+# ---------------------------------------------------------------- P3 chords
+
+def test_p3_uniform_box_chord(orc):
+    """Uniform static emissivity in a cell-aligned sub-box: I = j x chord."""
+    n = 10
+    j = np.zeros((1, n, n, n))
+    lo, hi = np.array([2, 3, 1]), np.array([7, 9, 6])  # x, y, z cells [lo, hi)
+    j[0, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = 1.7
+    s = _stack(orc, j, np.zeros((1, n, n, n, 3)), [0.0])
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        th, ph = rng.uniform(5, 175), rng.uniform(0, 360)
+        v = orc.View(th, ph, 24, 24, 0.61, 0.0, 0.7, orc.NO_LOOKBACK | orc.NO_BEAMING)
+        img, _ = orc.render(s, v, threads=2)
+        for (i, jj) in [(3, 4), (12, 12), (11, 15), (20, 2), (7, 19)]:
+            o, d = _ray(v, (n, n, n), (1, 1, 1), i, jj)
+            want = 1.7 * _box_chord(o, d, lo.astype(float), hi.astype(float))
+            assert img[jj, i] == pytest.approx(want, rel=1e-12, abs=1e-12)
+
+
+def test_p3_chords_tile_the_ray(orc):
+    n = 9
+    s = _stack(orc, np.zeros((1, n, n, n)), np.zeros((1, n, n, n, 3)), [0.0])
+    v = orc.View(37.0, 211.0, 16, 16, 0.8, 0.0, 0.0, orc.NO_LOOKBACK)
+    for (i, jj) in [(8, 8), (5, 10), (10, 5)]:
+        seg = orc.segments(s, v, i, jj)
+        o, d = _ray(v, (n, n, n), (1, 1, 1), i, jj)
+        total = _box_chord(o, d, np.zeros(3), np.full(3, float(n)))
+        assert total > 1.0 and len(seg) > 3
+        assert seg[:, 1].max() - seg[:, 0].min() == pytest.approx(total, rel=1e-12)
+        np.testing.assert_allclose(seg[1:, 0], seg[:-1, 1], rtol=0, atol=1e-12)
+        assert np.sum(seg[:, 1] - seg[:, 0]) == pytest.approx(total, rel=1e-12)
+
+
+# ---------------------------------------------------------------- P4 O1 == O2
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_p4_sorted_planes_equal_brute_force(orc, seed):
+    rng = np.random.default_rng(100 + seed)
+    dims = (8 + seed, 7, 9 - seed)
+    j, beta, t = synth.random_stack(dims, 5, seed=seed, beta_max=0.95)
+    s = _stack(orc, j, beta, t, cell=(1.0, 1.3, 0.8))
+    L = synth.diag(dims)
+    for flags in (0, orc.NEAREST, orc.NO_LOOKBACK):
+        th, ph = rng.uniform(0, 180), rng.uniform(0, 360)
+        t_obs = float(t[0] + 0.5 * (t[-1] - t[0]))
+        v = orc.View(th, ph, 20, 18, 1.1 * L / 20, t_obs, 0.6, flags)
+        a, sa = orc.render(s, v, threads=2)
+        b, sb = orc.render_brute(s, v, threads=2)
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-13 * np.abs(b).max())
+        assert sa == sb
+
+
+# ---------------------------------------------------------------- P5 linear in time
+
+def test_p5_linear_in_time_closed_form(orc):
+    """j_m = a + b t_m (linear in time): Eq. 7 reproduces it exactly, so along
+    a cardinal ray I = sum_x dx (a + b tbar_x) with tbar_x = t_obs + (x_c - C)."""
+    n = 10
+    rng = np.random.default_rng(7)
+    a = rng.uniform(1, 2, size=(n, n, n))
+    b = rng.uniform(-0.2, 0.2, size=(n, n, n))
+    times = np.array([-8.0, -3.0, 0.5, 2.0, 9.0])
+    j = a[None] + b[None] * times[:, None, None, None]
+    s = _stack(orc, j, np.zeros((5, n, n, n, 3)), times)
+    t_obs = 0.3
+    # s_hat = -x: the ray enters at x = n and leaves at x = 0; s = C_x - x
+    v = orc.View(90.0, 0.0, n, n, 1.0, t_obs, 0.0, orc.NO_BEAMING)
+    img, _ = orc.render(s, v, threads=2)
+    xc = np.arange(n) + 0.5
+    tbar = t_obs + (xc - n / 2)
+    want = (a + b * tbar[None, None, :]).sum(axis=2)
+    np.testing.assert_allclose(img, want, rtol=1e-13)
+
+
+def test_p5_uniform_linear_field_oblique(orc):
+    """Spatially uniform j(t) = a + b t: I = integral over the chord of
+    a + b (t_obs - s) ds, a closed form at any orientation."""
+    n = 8
+    times = np.array([-20.0, -5.0, 4.0, 20.0])
+    a, b = 1.3, 0.07
+    j = np.broadcast_to((a + b * times)[:, None, None, None], (4, n, n, n)).copy()
+    s = _stack(orc, j, np.zeros((4, n, n, n, 3)), times)
+    v = orc.View(41.0, 17.0, 12, 12, 1.05, 0.4, 0.0, orc.NO_BEAMING)
+    img, _ = orc.render(s, v, threads=2)
+    for (i, jj) in [(6, 6), (3, 8), (9, 4)]:
+        o, d = _ray(v, (n, n, n), (1, 1, 1), i, jj)
+        C = np.full(3, n / 2)
+        # chord [s0, s1] along the ray measured from the plane through C
+        lo, hi = np.zeros(3), np.full(3, float(n))
+        ss = []
+        for k in range(3):
+            ss += [(lo[k] - o[k]) / d[k], (hi[k] - o[k]) / d[k]]
+        ss = np.array(ss).reshape(3, 2)
+        s0, s1 = np.max(ss.min(axis=1)), np.min(ss.max(axis=1))
+        assert s1 > s0 + 1.0  # every chosen pixel crosses the grid
+        want = (a + b * v.t_obs) * (s1 - s0) - b * (s1 ** 2 - s0 ** 2) / 2
+        assert np.allclose(o - C, (o - C) - np.dot(o - C, d) * d)  # o lies on the plane
+        assert img[jj, i] == pytest.approx(want, rel=1e-13)
+
+
+def test_p5_quadrature_agrees_for_linear_fields(orc):
+    n = 8
+    rng = np.random.default_rng(9)
+    a = rng.uniform(1, 2, size=(n, n, n))
+    b = rng.uniform(-0.1, 0.1, size=(n, n, n))
+    times = np.array([-10.0, -2.0, 3.0, 10.0])
+    j = a[None] + b[None] * times[:, None, None, None]
+    beta = np.zeros((4, n, n, n, 3))
+    beta[..., 2] = 0.5  # static, uniform: D^p static
+    s = _stack(orc, j, beta, times)
+    v = orc.View(63.0, 29.0, 10, 10, 1.3, 0.0, 0.7, 0)
+    img, _ = orc.render(s, v, threads=1)
+    h = 2e-4
+    for (i, jj) in [(5, 5), (3, 6)]:
+        q = orc.quadrature(s, v, i, jj, h=h)
+        nseg = len(orc.segments(s, v, i, jj))
+        gmax = np.abs(j).max() * orc.doppler([0, 0, 0.5], _ray(v, (n,) * 3, (1,) * 3, i, jj)[1]) ** 2.7
+        # midpoint quadrature with jumps at faces: at most one step misassigned per face
+        assert abs(img[jj, i] - q) <= 2 * h * gmax * (nseg + 1)
+
+
+# ---------------------------------------------------------------- P6 Doppler
+
+@pytest.mark.parametrize("bvec", [(0, 0, 0.6), (0.3, -0.5, 0.2), (0.0, 0.0, 0.995)])
+def test_p6_uniform_velocity(orc, bvec):
+    n = 8
+    jv = 0.9
+    beta = np.zeros((1, n, n, n, 3))
+    beta[...] = bvec
+    s = _stack(orc, np.full((1, n, n, n), jv), beta, [0.0])
+    alpha = 0.7
+    for th, ph in [(30.0, 0.0), (120.0, 75.0), (0.0, 0.0)]:
+        v = orc.View(th, ph, 10, 10, 1.2, 0.0, alpha, orc.NO_LOOKBACK)
+        img, _ = orc.render(s, v, threads=1)
+        for (i, jj) in [(5, 5), (2, 7)]:
+            o, d = _ray(v, (n,) * 3, (1,) * 3, i, jj)
+            chord = _box_chord(o, d, np.zeros(3), np.full(3, float(n)))
+            b = np.array(bvec, float)
+            D = math.sqrt(1 - b @ b) / (1 + b @ d)
+            assert img[jj, i] == pytest.approx(jv * D ** (2 + alpha) * chord, rel=1e-13, abs=1e-15)
+
+
+def test_p6_doppler_closed_forms(orc):
+    # head-on approach: D = sqrt((1 + b) / (1 - b)); Gamma = 2 -> b = 0.8660254
+    b = math.sqrt(0.75)
+    assert orc.doppler([0, 0, b], [0, 0, -1]) == pytest.approx(math.sqrt((1 + b) / (1 - b)), rel=1e-14)
+    assert orc.doppler([0, 0, b], [-1, 0, 0]) == pytest.approx(1 / orc.lorentz(b), rel=1e-14)
+
+
+# ---------------------------------------------------------------- P7 midpoint vs continuous
+
+def test_p7_midpoint_error_bound(orc):
+    """General fields: O1 (retarded time at each chord midpoint) differs from
+    the continuous integral (O3) by at most the midpoint-rule error of the
+    kinks of the piecewise-linear time interpolation inside each chord."""
+    n = 7
+    j, beta, t = synth.random_stack((n, n, n), 9, seed=4, beta_max=0.0,
+                                    times=np.linspace(-6, 6, 9))
+    s = _stack(orc, j, beta, t)
+    v = orc.View(52.0, 33.0, 9, 9, 1.25, 0.0, 0.0, orc.NO_BEAMING)
+    img, _ = orc.render(s, v, threads=1)
+    h = 1e-4
+    M = len(t)
+    jf = j.reshape(M, -1)
+    for (i, jj) in [(4, 4), (2, 5), (6, 3)]:
+        seg = orc.segments(s, v, i, jj)
+        bound = 2 * h * np.abs(j).max() * (len(seg) + 1)
+        for sa, sb, c in seg:
+            ta, tb = v.t_obs - sb, v.t_obs - sa
+            slopes = np.diff(jf[:, int(c)]) / np.diff(t)
+            for m in range(1, M - 1):
+                if ta < t[m] < tb:
+                    bound += abs(slopes[m] - slopes[m - 1]) * (sb - sa) ** 2 / 8
+        q = orc.quadrature(s, v, i, jj, h=h)
+        assert abs(img[jj, i] - q) <= bound * 1.0001
+        # and the first-order alternative (entry-point sampling) would not fit:
+        # at least one ray must see a kink at all for the test to mean something
+    assert bound > 2 * h * np.abs(j).max() * (len(seg) + 1)
+
+
+# ---------------------------------------------------------------- P8 fast-light limit
+
+def test_p8_fast_light_limit(orc):
+    """c -> infinity (Eq. 3, Eq. 10): scaling every time by K makes the light
+    crossing negligible, so lookback rendering tends to the NO_LOOKBACK image."""
+    n = 8
+    j, beta, t = synth.random_stack((n, n, n), 6, seed=8, beta_max=0.9)
+    t_obs = 0.37 * t[0] + 0.63 * t[-1]
+    s_fast = _stack(orc, j, beta, t)
+    v_fast = orc.View(70.0, 40.0, 12, 12, 1.1, t_obs, 0.6, orc.NO_LOOKBACK)
+    ref, _ = orc.render(s_fast, v_fast, threads=1)
+    K = 1e9
+    s_slow = _stack(orc, j, beta, t * K)
+    v_slow = orc.View(70.0, 40.0, 12, 12, 1.1, t_obs * K, 0.6, 0)
+    got, _ = orc.render(s_slow, v_slow, threads=1)
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-9 * np.abs(ref).max())
+    # and without the scaling the two differ (lookback matters at c = 1)
+    s_one = _stack(orc, j, beta, t)
+    v_one = orc.View(70.0, 40.0, 12, 12, 1.1, t_obs, 0.6, 0)
+    one, _ = orc.render(s_one, v_one, threads=1)
+    assert np.abs(one - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- P9 rotation invariance
+
+def test_p9_flux_rotation_invariance(orc):
+    """beta = 0 and static epochs: total flux = sum_cells j V_cell at any view
+    (orthographic projection conserves the volume integral)."""
+    n = 10
+    rng = np.random.default_rng(21)
+    J = rng.uniform(0.2, 1.0, size=(n, n, n))
+    s = _stack(orc, J[None], np.zeros((1, n, n, n, 3)), [0.0])
+    want = J.sum()
+    L = synth.diag((n, n, n))
+    P = 200
+    # Oblique views only: there the image is continuous (chords shrink to zero
+    # at the silhouette) and the pixel-centre quadrature converges at second
+    # order.  A cardinal view has a constant chord up to the grid edge, a jump
+    # that pixel sampling resolves only to first order in the pixel size.
+    for th, ph in [(33.0, 10.0), (71.0, 133.0), (150.0, 250.0)]:
+        v = orc.View(th, ph, P, P, 1.01 * L / P, 0.0, 0.6, orc.NO_LOOKBACK)
+        img, _ = orc.render(s, v)
+        assert orc.flux(img, v) == pytest.approx(want, rel=3e-4)
+
+
+# ---------------------------------------------------------------- P10-P12 twin ejecta
+
+EJ = dict(dims=(28, 28, 104), radius=6.0, gamma=2.0, axis_sep=8.0)
+
+
+def _ejecta(orc, times, **kw):
+    """Mock of Sec. 3: the approaching ejectum's image draws on epochs up to
+    t_obs + ~40 (its apparent extent along the line of sight is stretched by
+    1 / (1 - beta cos theta) = 2.58), hence the long z axis and epoch range."""
+    p = dict(EJ)
+    p.update(kw)
+    j, b, t = synth.twin_ejecta(dims=p["dims"], radius=p["radius"], gamma=p["gamma"],
+                                times=times, t_centre=0.0, sub=4, axis_sep=p["axis_sep"])
+    return _stack(orc, j.astype(np.float32), b.astype(np.float32), t), p
+
+
+def _split_flux(img, v, v_split):
+    rows = (np.arange(img.shape[0]) + 0.5 - img.shape[0] / 2) * v.pixel_scale
+    up = img[rows > v_split].sum() * v.pixel_scale ** 2
+    down = img[rows < v_split].sum() * v.pixel_scale ** 2
+    return up, down
+
+
+def test_p10_routine_b_flux_ratio_exact(orc):
+    """Routine B (beaming, no lookback) on point-symmetric ejecta: flux ratio
+    = (D_adv / D_rec)^p exactly (Sec. 3.1, Table 1: 40.70 for p = 2.6)."""
+    s, p = _ejecta(orc, [0.0])
+    v = orc.View(45.0, 0.0, 96, 96, 0.5, 0.0, 0.6, orc.NO_LOOKBACK)
+    img, _ = orc.render(s, v)
+    up, down = _split_flux(img, v, 0.0)
+    b = float(np.float32(math.sqrt(0.75)))
+    want = ((1 + b * math.cos(math.pi / 4)) / (1 - b * math.cos(math.pi / 4))) ** 2.6
+    assert up / down == pytest.approx(want, rel=1e-12)
+    assert up / down == pytest.approx(40.70, abs=0.01)   # the paper's printed value
+    # routine A: no beaming, equal fluxes
+    va = orc.View(45.0, 0.0, 96, 96, 0.5, 0.0, 0.6, orc.NO_LOOKBACK | orc.NO_BEAMING)
+    ia, _ = orc.render(s, va)
+    ua, da = _split_flux(ia, va, 0.0)
+    assert ua / da == pytest.approx(1.0, rel=1e-12)
+
+
+@pytest.fixture(scope="module")
+def ejecta_c(orc):
+    times = np.arange(-12.0, 48.0 + 1e-9, 1.0)
+    s, p = _ejecta(orc, times)
+    return s
+
+
+def test_p10_routine_c_flux_ratio(orc, ejecta_c):
+    """Routine C (beaming + lookback): the ratio tends to D^(3+alpha), i.e.
+    169.27 at theta = 45 deg, Gamma = 2 (Eq. 23, Table 1)."""
+    v = orc.View(45.0, 0.0, 128, 128, 0.4, 0.0, 0.6, 0)
+    img, _ = orc.render(ejecta_c, v)
+    up, down = _split_flux(img, v, _gap_split(img, v))
+    theory = orc.flux_ratio(math.sqrt(0.75), math.pi / 4, 3.6)
+    assert theory == pytest.approx(169.27, abs=0.01)
+    assert up / down == pytest.approx(theory, rel=0.02)
+    # total flux of each ejectum: D^(3+alpha) times the rest-frame volume
+    V = 4 / 3 * math.pi * EJ["radius"] ** 3
+    b = math.sqrt(0.75)
+    D_adv = 1 / (2 * (1 - b * math.cos(math.pi / 4)))
+    D_rec = 1 / (2 * (1 + b * math.cos(math.pi / 4)))
+    assert up == pytest.approx(V * D_adv ** 3.6, rel=0.02)
+    assert down == pytest.approx(V * D_rec ** 3.6, rel=0.02)
+
+
+def _centroid_v(img, v, lo, hi):
+    rows = (np.arange(img.shape[0]) + 0.5 - img.shape[0] / 2) * v.pixel_scale
+    w = img.sum(axis=1)
+    sel = (rows > lo) & (rows < hi)
+    return float((rows[sel] * w[sel]).sum() / w[sel].sum())
+
+
+def _gap_split(img, v):
+    """Row coordinate in the middle of the widest empty band between the two images."""
+    rows = (np.arange(img.shape[0]) + 0.5 - img.shape[0] / 2) * v.pixel_scale
+    nz = np.where(img.sum(axis=1) > 0)[0]
+    k = int(np.argmax(np.diff(nz)))
+    assert nz[k + 1] - nz[k] > 1, "the two ejecta must image apart"
+    return 0.5 * (rows[nz[k]] + rows[nz[k + 1]])
+
+
+def test_p11_apparent_transverse_speed(orc, ejecta_c):
+    """Eq. 21: centroids move at beta sin th / (1 -+ beta cos th) with lookback
+    (1.580 advancing, 0.380 receding; the paper reads ~1.6 / ~0.4) and at
+    beta sin th (0.612, the paper's ~0.6) without."""
+    b, th = math.sqrt(0.75), math.pi / 4
+    t1, t2 = 0.0, 6.0
+    cs = {}
+    for flags in (0, orc.NO_LOOKBACK):
+        for t in (t1, t2):
+            v = orc.View(45.0, 0.0, 160, 160, 0.4, t, 0.6, flags | orc.NO_BEAMING)
+            img, _ = orc.render(ejecta_c, v)
+            split = _gap_split(img, v) if flags == 0 else 0.0
+            cs[(flags, t)] = (_centroid_v(img, v, split, 99), _centroid_v(img, v, -99, split))
+    adv = (cs[(0, t2)][0] - cs[(0, t1)][0]) / (t2 - t1)
+    rec = (cs[(0, t2)][1] - cs[(0, t1)][1]) / (t2 - t1)
+    assert adv == pytest.approx(orc.apparent_speed(b, th), rel=0.01)
+    assert -rec == pytest.approx(b * math.sin(th) / (1 + b * math.cos(th)), rel=0.01)
+    adv0 = (cs[(1, t2)][0] - cs[(1, t1)][0]) / (t2 - t1)
+    rec0 = (cs[(1, t2)][1] - cs[(1, t1)][1]) / (t2 - t1)
+    assert adv0 == pytest.approx(b * math.sin(th), rel=0.01)
+    assert -rec0 == pytest.approx(b * math.sin(th), rel=0.01)
+    assert orc.apparent_speed(b, th) == pytest.approx(1.580, abs=1e-3)
+    # superluminal: at theta_crit = acos(beta) the apparent speed peaks at Gamma beta
+    tc = math.acos(b)
+    assert orc.apparent_speed(b, tc) == pytest.approx(2 * b, rel=1e-12)
+    assert orc.apparent_speed(b, tc) > 1.0
+
+
+def _axis_ratio(img, v, lo, hi):
+    rows = (np.arange(img.shape[0]) + 0.5 - img.shape[0] / 2) * v.pixel_scale
+    cols = (np.arange(img.shape[1]) + 0.5 - img.shape[1] / 2) * v.pixel_scale
+    sel = (rows > lo) & (rows < hi)
+    w = img[sel]
+    V, U = np.meshgrid(rows[sel], cols, indexing="ij")
+    m = w.sum()
+    cv, cu = (w * V).sum() / m, (w * U).sum() / m
+    return math.sqrt(((w * (V - cv) ** 2).sum() / m) / ((w * (U - cu) ** 2).sum() / m))
+
+
+def test_p12_penrose_terrell(orc, ejecta_c):
+    """Sec. 3.3: with lookback a rest-frame sphere images as a circle; without
+    it, the lab-frame spheroid projects with axis ratio
+    sqrt(cos^2 th + sin^2 th / Gamma^2) = 0.79 at 45 deg, Gamma = 2."""
+    v = orc.View(45.0, 0.0, 160, 160, 0.4, 0.0, 0.6, orc.NO_BEAMING)
+    img, _ = orc.render(ejecta_c, v)
+    assert _axis_ratio(img, v, _gap_split(img, v), 99) == pytest.approx(1.0, abs=0.05)
+    v0 = orc.View(45.0, 0.0, 160, 160, 0.4, 0.0, 0.6, orc.NO_BEAMING | orc.NO_LOOKBACK)
+    img0, _ = orc.render(ejecta_c, v0)
+    want = math.sqrt(0.5 + 0.5 / 4)
+    assert want == pytest.approx(0.79, abs=0.005)
+    assert _axis_ratio(img0, v0, 0.0, 99) == pytest.approx(want, abs=0.04)
+
+
+# ---------------------------------------------------------------- P13 linearity, symmetry
+
+def test_p13_linearity(orc):
+    n = 8
+    j1, beta, t = synth.random_stack((n, n, n), 4, seed=31, beta_max=0.8)
+    j2, _, _ = synth.random_stack((n, n, n), 4, seed=32, beta_max=0.8)
+    v = orc.View(58.0, 140.0, 12, 12, 1.2, float(t.mean()), 0.7, 0)
+    r1, _ = orc.render(_stack(orc, j1, beta, t), v, threads=1)
+    r2, _ = orc.render(_stack(orc, j2, beta, t), v, threads=1)
+    r12, _ = orc.render(_stack(orc, 2.0 * j1 - 0.5 * j2, beta, t), v, threads=1)
+    np.testing.assert_allclose(r12, 2.0 * r1 - 0.5 * r2, rtol=1e-12, atol=1e-12)
+
+
+def test_p13_rotation_about_z(orc):
+    """Rotating the grid +90 deg about z (with beta) and the view phi -> phi+90
+    leaves the image unchanged."""
+    n = 8
+    j, beta, t = synth.random_stack((n, n, n), 4, seed=41, beta_max=0.8)
+    # new[x', y'] = old[x, y] with x' = n-1-y, y' = x; beta' = R beta, R = rot(+90)
+    jr = np.empty_like(j)
+    br = np.empty_like(beta)
+    for x in range(n):
+        for y in range(n):
+            jr[:, :, x, n - 1 - y] = j[:, :, y, x]
+            br[:, :, x, n - 1 - y, 0] = -beta[:, :, y, x, 1]
+            br[:, :, x, n - 1 - y, 1] = beta[:, :, y, x, 0]
+            br[:, :, x, n - 1 - y, 2] = beta[:, :, y, x, 2]
+    tm = float(t.mean())
+    a, _ = orc.render(_stack(orc, j, beta, t), orc.View(50.0, 20.0, 12, 12, 1.1, tm, 0.7, 0), threads=1)
+    b, _ = orc.render(_stack(orc, jr, br, t), orc.View(50.0, 110.0, 12, 12, 1.1, tm, 0.7, 0), threads=1)
+    np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-13)
+
+
+def test_p13_mirror_z(orc):
+    """Mirroring z (beta_z -> -beta_z) and theta -> 180 - theta reverses the
+    image rows."""
+    n = 8
+    j, beta, t = synth.random_stack((n, n, n), 4, seed=51, beta_max=0.8)
+    jm = j[:, ::-1].copy()
+    bm = beta[:, ::-1].copy()
+    bm[..., 2] *= -1
+    tm = float(t.mean())
+    a, _ = orc.render(_stack(orc, j, beta, t), orc.View(35.0, 60.0, 12, 12, 1.1, tm, 0.7, 0), threads=1)
+    b, _ = orc.render(_stack(orc, jm, bm, t), orc.View(145.0, 60.0, 12, 12, 1.1, tm, 0.7, 0), threads=1)
+    np.testing.assert_allclose(b[::-1], a, rtol=1e-12, atol=1e-13)
+
+
+# ---------------------------------------------------------------- sample count
+
+def test_count_samples_small(orc):
+    """Distinct samples with positive weight, checked by an independent
+    enumeration over the oracle's chords."""
+    n = 6
+    j, beta, t = synth.random_stack((n, n, n), 4, seed=61, beta_max=0.5)
+    s = _stack(orc, j, beta, t)
+    v = orc.View(40.0, 30.0, 10, 10, 1.0, float(t.mean()), 0.7, 0)
+    seen = set()
+    for jj in range(10):
+        for i in range(10):
+            for sa, sb, c in orc.segments(s, v, i, jj):
+                for m, w in orc.epoch_weights(t, v.t_obs - 0.5 * (sa + sb)):
+                    if w > 0:
+                        seen.add((m, int(c)))
+    assert orc.count_samples(s, v) == len(seen)
