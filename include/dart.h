@@ -1,0 +1,246 @@
+/*
+ * dart.h -- C ABI of the MI355X lookback ray-marching library (libdart.so).
+ *
+ * The library evaluates, for every pixel of an orthographic image, the
+ * optically thin intensity sum of the paper's Eq. 19 (Sec. 2.5):
+ *
+ *     I = sum_n sum_m W_{n,m} D_{n,m}^p j_{n,m} ds_n ,      p = 2 + alpha
+ *
+ * over the cells n a pixel ray crosses (3D DDA, Sec. 2.4, Eq. 11), with the
+ * epoch pair m chosen at the cell's retarded time tbar_n = t_obs - s_n / c
+ * (Eq. 2, c = 1) and weighted linearly in time (Eqs. 6-7), and with the
+ * Doppler factor D = sqrt(1 - beta^2) / (1 + beta . s_hat) of Eq. 14.  Only
+ * cells whose retarded time lies inside the epoch coverage [t_0, t_{M-1}]
+ * are visited (the fast-forward of Sec. 5.1).  The output is at the reference
+ * frequency, so the prefactor (nu / nu0')^alpha of Eq. 19 is 1.
+ *
+ * Conventions shared by every call:
+ *  - alpha is the positive index of S ~ nu^-alpha; the per-cell exponent is
+ *    p = 2 + alpha (the paper writes 2 - alpha with alpha = -0.6 by default).
+ *  - Lengths are in the caller's unit; times are in that unit / c.
+ *  - The grid spans [0, nx dx) x [0, ny dy) x [0, nz dz); cells are half-open.
+ *  - theta is the polar angle (degrees) of the direction toward the observer
+ *    n_hat = (sin th cos ph, sin th sin ph, cos th) from +z, phi its azimuth
+ *    from +x; rays travel along s_hat = -n_hat.  Image axes:
+ *    e_u = (-sin ph, cos ph, 0) (columns), e_v = (-cos th cos ph,
+ *    -cos th sin ph, sin th) (rows).  Pixel (i, j) has its ray through
+ *    C + (i + 1/2 - W/2) ps e_u + (j + 1/2 - H/2) ps e_v, C the grid centre;
+ *    row 0 is the bottom row.  Images are row-major [height][width].
+ *  - s is measured along the ray from the plane through C normal to s_hat;
+ *    the retarded time of a cell is t_obs - s_mid with s_mid its chord
+ *    midpoint.  Cells with s_mid outside the epoch coverage contribute 0.
+ *  - Flux = sum of pixel intensities x ps^2 (Eq. 22 up to 1/L^2).
+ *  - One cell-step = one (ray, cell) pair with a positive chord inside the
+ *    temporal window.
+ *
+ * Errors: every call returns a dart_status; no exception crosses the ABI.  On
+ * error the outputs are left untouched (and *out = NULL for constructors) and
+ * dart_last_error() returns a thread-local message.
+ *
+ * Threading: stacks are read-only after loading and may be rendered from
+ * several host threads and streams at once.  The server object is
+ * thread-safe.  Every call uses the HIP device that is current on the calling
+ * thread; a stack must be rendered on the device it was loaded on.
+ */
+#ifndef DART_H
+#define DART_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DART_OK = 0,
+    DART_E_INVAL = -1,    /* malformed argument */
+    DART_E_RANGE = -2,    /* |beta| >= 1 or a non-finite value in the fields */
+    DART_E_NOMEM = -3,    /* device or host allocation failed / over budget */
+    DART_E_DEVICE = -4,   /* a HIP runtime call failed */
+    DART_E_BUSY = -5,     /* object still in use (renders in flight, full queue) */
+    DART_E_INTERNAL = -6
+} dart_status;
+
+typedef enum { DART_F64 = 0, DART_F32 = 1, DART_F16 = 2, DART_BF16 = 3 } dart_dtype;
+
+/* flags (dart_view.flags, and the load flags where noted) */
+#define DART_NO_LOOKBACK 0x1u   /* routine B: tbar = t_obs for every cell (Eq. 3, Eq. 10) */
+#define DART_NO_BEAMING 0x2u    /* routine A: D = 1 */
+#define DART_NEAREST_EPOCH 0x4u /* weight 1 on the epoch closest to tbar (ties: earlier) */
+#define DART_NO_KAHAN 0x8u      /* plain (uncompensated) FP32 accumulation */
+#define DART_FORCE_F64_DDA 0x10u /* FP64 ray parameters and FP64 D^p even for 16/32-bit stacks */
+#define DART_DEVICE_PTRS 0x20u  /* load: field pointers are device pointers;
+                                   view: the image pointer is a device pointer */
+#define DART_KERNEL_PLAIN 0x40u /* dart_render_batch: force the one-launch-per-image kernel */
+
+typedef struct dart_stack dart_stack;
+typedef struct dart_server dart_server;
+
+/* ---------------------------------------------------------------- stacks --
+ * dart_load_epochs: copy M epochs of emissivity j'_{nu0'} and velocity beta
+ * (the method's inputs, Sec. 2.5) into a resident device stack.
+ *   dims[3]      nx, ny, nz > 0 (cells)
+ *   cell[3]      dx, dy, dz > 0 and finite
+ *   n_epochs     M >= 1;  epoch_times[M] finite and strictly increasing
+ *   src_dtype    DART_F64 or DART_F32: element type of the two arrays
+ *   storage      resident element type; DART_F16 / DART_BF16 round to nearest even
+ *   emissivity   [M][nz][ny][nx], C order (x fastest)
+ *   velocity     [M][nz][ny][nx][3] (beta_x, beta_y, beta_z)
+ *   flags        DART_DEVICE_PTRS: arrays are device memory; the copy is
+ *                stream-ordered and the caller keeps them alive until the
+ *                stream passes this call.  Host arrays: the call returns after
+ *                the copy has finished.
+ *   hip_stream   hipStream_t or NULL (default stream)
+ * Every value must be finite and |beta| < 1 before and after rounding to the
+ * storage type, else DART_E_RANGE names the first bad element.
+ * The stack owns its device memory until dart_free_epochs.
+ */
+dart_status dart_load_epochs(const int32_t dims[3], const double cell[3], int32_t n_epochs,
+                             const double *epoch_times, dart_dtype src_dtype, dart_dtype storage,
+                             const void *emissivity, const void *velocity, uint32_t flags,
+                             void *hip_stream, dart_stack **out);
+
+/* Two-phase loading for stacks that cannot be staged whole: create an empty
+ * stack, then fill epochs [m0, m0 + count) from arrays laid out as
+ * [count][nz][ny][nx] and [count][nz][ny][nx][3].  A stack can be rendered once
+ * every epoch has been filled (DART_E_INVAL otherwise). */
+dart_status dart_stack_create(const int32_t dims[3], const double cell[3], int32_t n_epochs,
+                              const double *epoch_times, dart_dtype storage, uint32_t flags,
+                              dart_stack **out);
+dart_status dart_stack_set_epochs(dart_stack *s, int32_t m0, int32_t count, dart_dtype src_dtype,
+                                  const void *emissivity, const void *velocity, uint32_t flags,
+                                  void *hip_stream);
+
+/* Releases the stack; DART_E_BUSY (and nothing freed) while a render that
+ * reads it is still running on the device. */
+dart_status dart_free_epochs(dart_stack *s);
+
+typedef struct {
+    int32_t dims[3];
+    int32_t n_epochs;
+    dart_dtype storage;
+    int32_t brick[3];      /* resident brick shape (cells) */
+    uint64_t device_bytes; /* resident bytes */
+} dart_stack_info;
+dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info *info);
+
+/* Re-lays the resident stack with a new brick shape (powers of two, each
+ * 1..16, at most 4096 cells per brick).  Needs the stack's size again in free
+ * device memory while it runs. */
+dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3], void *hip_stream);
+
+/* ---------------------------------------------------------------- render --
+ * One observation (N cameras per call in the batch form).
+ *   theta_deg, phi_deg  orientation (finite)
+ *   width, height       image size in pixels (> 0)
+ *   pixel_scale         length per pixel (> 0, finite)
+ *   t_obs               observer time
+ *   alpha               spectral index, p = 2 + alpha (finite)
+ *   flags               DART_NO_LOOKBACK | DART_NO_BEAMING | DART_NEAREST_EPOCH |
+ *                       DART_NO_KAHAN | DART_FORCE_F64_DDA | DART_DEVICE_PTRS
+ *   out_dtype           DART_F32, or DART_F64 (FP64 stacks only)
+ */
+typedef struct {
+    double theta_deg, phi_deg;
+    int32_t width, height;
+    double pixel_scale;
+    double t_obs;
+    double alpha;
+    uint32_t flags;
+    dart_dtype out_dtype;
+} dart_view;
+
+/* Plain kernel: one launch, one thread per pixel.
+ *   image      [height][width] of out_dtype; host memory unless the view has
+ *              DART_DEVICE_PTRS (then stream-ordered)
+ *   flux_out   nullable host pointer: sum I ps^2
+ *   steps_out  nullable host pointer: cell-steps of the image
+ * With a host image or a non-NULL flux_out/steps_out the call waits for the
+ * stream; otherwise it returns once the work is enqueued. */
+dart_status dart_render(const dart_stack *s, const dart_view *v, void *image, double *flux_out,
+                        uint64_t *steps_out, void *hip_stream);
+
+/* Batched form: n (stack, view, image) triples rendered by one persistent,
+ * tile-queue launch per (storage type, precision) group.  Stacks may differ.
+ * images[i] follows views[i].flags like dart_render; flux_out[n] and
+ * steps_out[n] are nullable host arrays.  A call whose arguments equal those of
+ * the previous call on the same stream replays a captured hipGraph. */
+dart_status dart_render_batch(const dart_stack *const *stacks, const dart_view *views, int32_t n,
+                              void *const *images, double *flux_out, uint64_t *steps_out,
+                              void *hip_stream);
+
+/* Launch-shape parameters of the batched kernel (see dart_autotune). */
+typedef struct {
+    int32_t tile_w, tile_h;  /* pixels per wavefront tile, tile_w * tile_h == 64 */
+    int32_t waves_per_cu;    /* resident waves per compute unit for the persistent grid */
+    int32_t order;           /* 0: tiles in spatial order, 1: longest estimated tile first */
+} dart_tuning;
+
+/* Times the batched kernel on the given views over candidate tile shapes,
+ * occupancies, tile orders and (if rebrick != 0) brick shapes, and keeps the
+ * fastest for later dart_render_batch calls on these stacks.  best_out and
+ * best_ms_out are nullable. */
+dart_status dart_autotune(dart_stack *const *stacks, const dart_view *views, int32_t n,
+                          int32_t rebrick, dart_tuning *best_out, double *best_ms_out,
+                          void *hip_stream);
+dart_status dart_set_tuning(const dart_tuning *t);
+dart_status dart_get_tuning(dart_tuning *t);
+
+/* Number of distinct (cell, epoch) samples that receive a positive weight on
+ * any ray of the image: the compulsory stack bytes of a render are this count
+ * times the record size.  Untimed instrumentation (bitmap + counting pass). */
+dart_status dart_count_samples(const dart_stack *s, const dart_view *v, uint64_t *samples_out,
+                               void *hip_stream);
+
+/* Bytes of one resident record (j, beta_x, beta_y, beta_z) of a stack. */
+dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_out);
+
+/* Streaming copy of `bytes` (multiple of 16) from src to dst, both device
+ * memory: the measured HBM bandwidth reference. reps > 0 copies are enqueued. */
+dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t bytes, int32_t reps,
+                                 void *hip_stream);
+
+/* ---------------------------------------------------------------- serving --
+ * A render server keeps stacks resident (the caller's) and runs a host
+ * scheduler thread that batches requests as they arrive (continuous batching):
+ * every admitted, unfinished request is rendered by the next wave, waves run
+ * on several streams and overlap on the device.  Output images are staged in
+ * server-owned device memory; admission waits until the staged images of the
+ * requests in flight fit in hbm_budget_bytes and fewer than max_inflight are
+ * running.
+ *   image      destination [height][width] float32 (host memory, or device
+ *              memory with DART_DEVICE_PTRS in the view flags); must stay valid
+ *              until the ticket completes.
+ *   ticket     out: identifies the request.
+ * dart_poll: done = 1 once the image is written; flux and latency (ms from
+ * submission to completion) are then valid.  dart_wait blocks until done.
+ * dart_server_destroy waits for every request.
+ */
+dart_status dart_server_create(size_t hbm_budget_bytes, int32_t max_inflight, int32_t n_streams,
+                               dart_server **out);
+dart_status dart_submit(dart_server *srv, const dart_stack *s, const dart_view *v, void *image,
+                        uint64_t *ticket);
+dart_status dart_poll(dart_server *srv, uint64_t ticket, int32_t *done, double *flux,
+                      double *latency_ms);
+dart_status dart_wait(dart_server *srv, uint64_t ticket, double *flux, double *latency_ms);
+dart_status dart_server_destroy(dart_server *srv);
+
+typedef struct {
+    uint64_t submitted, completed, waves;
+    uint64_t max_wave_requests;
+    uint64_t bytes_in_use, bytes_peak;
+    uint64_t admission_waits;  /* times a request waited for memory or a slot */
+} dart_server_stats;
+dart_status dart_server_get_stats(dart_server *srv, dart_server_stats *st);
+
+/* Thread-local text describing the last non-OK status on this thread. */
+const char *dart_last_error(void);
+
+/* Library version string. */
+const char *dart_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DART_H */

@@ -1,0 +1,85 @@
+// dart_internal.h -- descriptors shared by the HIP kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dart {
+
+enum Store : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+enum : uint32_t {
+    F_NO_LOOKBACK = 0x1u,
+    F_NO_BEAMING = 0x2u,
+    F_NEAREST = 0x4u,
+    F_NO_KAHAN = 0x8u,
+    F_F64_DDA = 0x10u,
+    F_DEVICE_PTRS = 0x20u,
+};
+
+// Resident stack as the kernels see it.  Records (j, bx, by, bz) are stored
+// epoch-major; inside an epoch the cells are grouped in bricks of
+// 2^lb[0] x 2^lb[1] x 2^lb[2] cells (x fastest inside a brick, bricks x-fastest).
+struct StackDev {
+    const void *data;       // resident records
+    const double *times;    // [M] epoch times (device)
+    uint64_t epoch_stride;  // records per epoch (padded to whole bricks)
+    int32_t n[3];           // cells per axis
+    int32_t nb[3];          // bricks per axis
+    int32_t lb[3];          // log2 of the brick shape
+    int32_t n_epochs;
+    int32_t store;          // Store
+    double cell[3];
+};
+
+// One view, resolved on the host in FP64.
+struct RayView {
+    double shat[3], eu[3], ev[3], centre[3];
+    double ps;              // pixel scale
+    double t_obs;
+    double s_lo, s_hi;      // temporal window expressed in s: [t_obs - t_{M-1}, t_obs - t_0]
+    double p;               // 2 + alpha
+    uint32_t flags;
+    int32_t width, height;
+    int32_t fixed_m;        // NO_LOOKBACK: epoch bracket at t_obs (-1: t_obs outside coverage)
+    double fixed_w;         // NO_LOOKBACK: weight of epoch fixed_m + 1
+    void *image;            // [height][width] float or double (device)
+    int32_t out_f64;
+    int32_t acc_index;      // slot in the flux / step accumulators
+    StackDev st;
+};
+
+struct Tile {
+    uint32_t view;
+    uint16_t tx, ty;
+};
+
+// Launch parameters of the persistent batched kernel.
+struct BatchLaunch {
+    const RayView *views;
+    const Tile *tiles;
+    uint32_t n_tiles;
+    uint32_t *head;         // tile queue heads, one per XCD queue
+    uint32_t n_queues;
+    uint32_t tile_w_log2;   // tile width = 1 << tile_w_log2, tile height = 64 >> tile_w_log2
+    double *flux_acc;
+    unsigned long long *step_acc;
+};
+
+// Host-side launchers (dart_kernels.hip).
+hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *step_acc,
+                        hipStream_t s);
+hipError_t launch_batch(int store, bool f64_dda, const BatchLaunch &bl, int grid_blocks,
+                        hipStream_t s);
+hipError_t launch_mark(const RayView &v, uint32_t *bitmap, hipStream_t s);
+hipError_t launch_popcount(const uint32_t *bitmap, uint64_t words, unsigned long long *out,
+                           hipStream_t s);
+hipError_t launch_convert(int src_f64, int store, const void *j, const void *beta, int32_t m0,
+                          int32_t count, const StackDev &st, void *data,
+                          unsigned long long *err, hipStream_t s);
+hipError_t launch_rebrick(int store, const StackDev &from, const StackDev &to, void *dst,
+                          hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,
+                           hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
+
+}  // namespace dart

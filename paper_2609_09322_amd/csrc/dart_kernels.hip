@@ -1,0 +1,635 @@
+// dart_kernels.hip -- gfx950 kernels of the lookback ray-marching hot path.
+//
+// Per pixel ray (paper Sec. 2.3-2.5, Eqs. 2, 4-11, 14, 18-19):
+//   * ray setup in FP64: pixel-centre origin, slab test against the grid box,
+//     clip to the temporal window [t_obs - t_{M-1}, t_obs - t_0] in s
+//     (the fast-forward of Sec. 5.1);
+//   * 3D DDA (Eq. 11): per axis the crossings of cell planes are equally spaced
+//     by ds_a = dx_a / |s_hat . x_a|; the k-th crossing is base_a + k ds_a,
+//     evaluated from the integer crossing count (no drift);
+//   * per cell: chord ds_n = exit - entry, retarded time at the chord midpoint,
+//     epoch pair by a monotone pointer (tbar only decreases along the ray),
+//     linear weight (Eqs. 6-7), two record gathers, D^p per epoch (Eq. 14 with
+//     p = 2 + alpha) and Kahan-compensated accumulation of Eq. 19.
+// The same device routine serves the one-launch-per-image kernel and the
+// persistent tile-queue kernel; a MARK instantiation records the (cell, epoch)
+// samples a render touches instead of summing them.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "dart_internal.h"
+
+namespace dart {
+
+// ------------------------------------------------------------------ records
+
+__device__ __forceinline__ uint32_t cell_offset(const StackDev &st, int x, int y, int z) {
+    const uint32_t bx = (uint32_t)x >> st.lb[0], by = (uint32_t)y >> st.lb[1],
+                   bz = (uint32_t)z >> st.lb[2];
+    const uint32_t lx = (uint32_t)x & ((1u << st.lb[0]) - 1u);
+    const uint32_t ly = (uint32_t)y & ((1u << st.lb[1]) - 1u);
+    const uint32_t lz = (uint32_t)z & ((1u << st.lb[2]) - 1u);
+    const uint32_t brick = (bz * (uint32_t)st.nb[1] + by) * (uint32_t)st.nb[0] + bx;
+    const uint32_t inner = (lz << (st.lb[0] + st.lb[1])) | (ly << st.lb[0]) | lx;
+    return (brick << (st.lb[0] + st.lb[1] + st.lb[2])) | inner;
+}
+
+template <int S> struct RecT;
+template <> struct RecT<ST_F64> { using raw = double4; using val = double; };
+template <> struct RecT<ST_F32> { using raw = float4; using val = float; };
+template <> struct RecT<ST_F16> { using raw = uint2; using val = float; };
+template <> struct RecT<ST_BF16> { using raw = uint2; using val = float; };
+
+template <int S>
+__device__ __forceinline__ typename RecT<S>::raw load_rec(const StackDev &st, uint64_t rec) {
+    const typename RecT<S>::raw *p = (const typename RecT<S>::raw *)st.data;
+    if constexpr (S == ST_F64) {
+        const double2 *q = (const double2 *)st.data;
+        double2 a = q[2 * rec], b = q[2 * rec + 1];
+        return double4{a.x, a.y, b.x, b.y};
+    } else {
+        return p[rec];
+    }
+}
+
+__device__ __forceinline__ float h2f(uint32_t bits16) {
+    return __half2float(__ushort_as_half((unsigned short)bits16));
+}
+
+template <int S, typename V>
+__device__ __forceinline__ void decode(const typename RecT<S>::raw &r, V &j, V &bx, V &by, V &bz) {
+    if constexpr (S == ST_F64 || S == ST_F32) {
+        j = r.x; bx = r.y; by = r.z; bz = r.w;
+    } else if constexpr (S == ST_F16) {
+        j = h2f(r.x & 0xffffu); bx = h2f(r.x >> 16); by = h2f(r.y & 0xffffu); bz = h2f(r.y >> 16);
+    } else {
+        j = __uint_as_float(r.x << 16); bx = __uint_as_float(r.x & 0xffff0000u);
+        by = __uint_as_float(r.y << 16); bz = __uint_as_float(r.y & 0xffff0000u);
+    }
+}
+
+// D^p j of one record (Eq. 14 raised to p, times the rest-frame emissivity).
+// FP64 stacks: all in FP64.  FP32 stacks: 1 - beta^2 and 1 + beta.s in FP64
+// (the two quantities that cancel at high Lorentz factor), logs in FP32.
+// 16-bit stacks: FP32 FMA chains starting from 1.
+template <int S>
+__device__ __forceinline__ typename RecT<S>::val boosted(const typename RecT<S>::raw &r,
+                                                        const RayView &v, bool beaming) {
+    using V = typename RecT<S>::val;
+    V j, bx, by, bz;
+    decode<S, V>(r, j, bx, by, bz);
+    if (!beaming || (bx == V(0) && by == V(0) && bz == V(0))) return j;
+    if constexpr (S == ST_F64) {
+        double q = fma(-bx, bx, fma(-by, by, fma(-bz, bz, 1.0)));
+        double rr = fma(bx, v.shat[0], fma(by, v.shat[1], fma(bz, v.shat[2], 1.0)));
+        return j * exp2(v.p * (0.5 * log2(q) - log2(rr)));
+    } else if constexpr (S == ST_F32) {
+        double dx = bx, dy = by, dz = bz;
+        double q = fma(-dx, dx, fma(-dy, dy, fma(-dz, dz, 1.0)));
+        double rr = fma(dx, v.shat[0], fma(dy, v.shat[1], fma(dz, v.shat[2], 1.0)));
+        float p = (float)v.p;
+        float e = fmaf(0.5f * p, __builtin_amdgcn_logf((float)q), -p * __builtin_amdgcn_logf((float)rr));
+        return j * __builtin_amdgcn_exp2f(e);
+    } else {
+        float q = fmaf(-bx, bx, fmaf(-by, by, fmaf(-bz, bz, 1.0f)));
+        float rr = fmaf(bx, (float)v.shat[0], fmaf(by, (float)v.shat[1], fmaf(bz, (float)v.shat[2], 1.0f)));
+        float p = (float)v.p;
+        float e = fmaf(0.5f * p, __builtin_amdgcn_logf(q), -p * __builtin_amdgcn_logf(rr));
+        return j * __builtin_amdgcn_exp2f(e);
+    }
+}
+
+// ------------------------------------------------------------------ one ray
+
+// Marches pixel (pi, pj) of view v.  Returns the intensity (FP64 for the
+// caller's reductions) and adds the counted cell-steps to nsteps.  With MARK
+// the (epoch, cell) samples of positive weight are set in `bitmap`
+// ([M][nz][ny][nx] bits) and nothing is summed.
+template <int S, typename R, bool MARK>
+__device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32_t *bitmap,
+                                        uint32_t &nsteps) {
+    using A = typename std::conditional<S == ST_F64, double, float>::type;
+    const StackDev &st = v.st;
+    const double u = (pi + 0.5 - 0.5 * v.width) * v.ps;
+    const double w = (pj + 0.5 - 0.5 * v.height) * v.ps;
+    double o[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) o[a] = v.centre[a] + u * v.eu[a] + w * v.ev[a];
+
+    // slab test against [0, n dx) per axis
+    double s_in = -INFINITY, s_out = INFINITY;
+    bool hit = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double d = v.shat[a];
+        const double hi = st.n[a] * st.cell[a];
+        if (d == 0.0) {
+            if (o[a] < 0.0 || o[a] >= hi) hit = false;
+        } else {
+            double t0 = (0.0 - o[a]) / d, t1 = (hi - o[a]) / d;
+            s_in = fmax(s_in, fmin(t0, t1));
+            s_out = fmin(s_out, fmax(t0, t1));
+        }
+    }
+    const double s_start = fmax(s_in, v.s_lo);
+    const double s_stop = fmin(s_out, v.s_hi);
+    if (!hit || !(s_start < s_stop) || !(s_in < s_out)) return 0.0;
+    if ((v.flags & F_NO_LOOKBACK) && v.fixed_m < 0) return 0.0;
+
+    // starting cell and per-axis crossing sequences
+    int idx[3], stp[3];
+    R base[3], dsa[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double d = v.shat[a];
+        const double x = o[a] + s_start * d;
+        int k = (int)floor(x / st.cell[a]);
+        k = k < 0 ? 0 : (k >= st.n[a] ? st.n[a] - 1 : k);
+        idx[a] = k;
+        if (d == 0.0) {
+            stp[a] = 0;
+            base[a] = (R)INFINITY;
+            dsa[a] = (R)0;
+        } else {
+            stp[a] = d > 0.0 ? 1 : -1;
+            const double plane = (d > 0.0 ? (k + 1) : k) * st.cell[a];
+            base[a] = (R)((plane - o[a]) / d);
+            dsa[a] = (R)(st.cell[a] / fabs(d));
+        }
+    }
+    // crossing counters: ahead plane = base + c ds, behind plane = base + (c - 1) ds
+    int c0 = 0, c1 = 0, c2 = 0;
+    R sa0 = base[0], sa1 = base[1], sa2 = base[2];
+    R sb0 = stp[0] ? base[0] - dsa[0] : (R)-INFINITY;
+    R sb1 = stp[1] ? base[1] - dsa[1] : (R)-INFINITY;
+    R sb2 = stp[2] ? base[2] - dsa[2] : (R)-INFINITY;
+    int x = idx[0], y = idx[1], z = idx[2];
+
+    const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi, r_stop = (R)s_stop;
+    const bool lookback = !(v.flags & F_NO_LOOKBACK);
+    const bool beaming = !(v.flags & F_NO_BEAMING);
+    const bool single = (v.flags & F_NEAREST) || st.n_epochs == 1;
+    const bool kahan = !(v.flags & F_NO_KAHAN);
+    const int M = st.n_epochs;
+
+    // epoch bracket in s: a_m = t_obs - t_m decreases with m; interval m holds
+    // a_{m+1} <= s_mid <= a_m.  NO_LOOKBACK uses the bracket at t_obs.
+    int m = lookback ? (M >= 2 ? M - 2 : 0) : v.fixed_m;
+    R am = (R)(v.t_obs - st.times[m]);
+    R am1 = M >= 2 ? (R)(v.t_obs - st.times[m + 1]) : am;
+    R inv_dt = M >= 2 ? (R)(1.0 / (st.times[m + 1] - st.times[m])) : (R)0;
+    const R fixed_w = (R)v.fixed_w;
+
+    A sum = 0, comp = 0;
+    uint32_t count = 0;
+    const uint64_t estride = st.epoch_stride;
+    // a ray visits at most nx + ny + nz cells; the cap makes termination
+    // independent of floating-point corner cases in the face selection
+    for (int guard = st.n[0] + st.n[1] + st.n[2] + 3; guard > 0; guard--) {
+        const R entry = fmax(sb0, fmax(sb1, sb2));
+        const R exit = fmin(sa0, fmin(sa1, sa2));
+        if (entry >= r_stop) break;
+        const R ds = exit - entry;
+        const R mid = (R)0.5 * (entry + exit);
+        if (ds > (R)0 && mid >= r_lo && mid <= r_hi) {
+            R wt;
+            if (lookback) {
+                while (m > 0 && mid > am) {
+                    m--;
+                    am1 = am;
+                    am = (R)(v.t_obs - st.times[m]);
+                    inv_dt = (R)(1.0 / (st.times[m + 1] - st.times[m]));
+                }
+                wt = (am - mid) * inv_dt;
+            } else {
+                wt = fixed_w;
+            }
+            int m0 = m;
+            if (single) {
+                if (M >= 2) {
+                    const bool later = lookback ? (mid - am1) < (am - mid) : wt > (R)0.5;
+                    m0 = later ? m + 1 : m;
+                }
+                wt = (R)0;
+            }
+            const uint32_t off = cell_offset(st, x, y, z);
+            count++;
+            if constexpr (MARK) {
+                const uint64_t ncell = (uint64_t)st.n[0] * st.n[1] * st.n[2];
+                const uint64_t lin = ((uint64_t)z * st.n[1] + y) * st.n[0] + x;
+                if (single || wt < (R)1) {
+                    const uint64_t b = (uint64_t)m0 * ncell + lin;
+                    atomicOr(&bitmap[b >> 5], 1u << (b & 31));
+                }
+                if (!single && wt > (R)0) {
+                    const uint64_t b = (uint64_t)(m0 + 1) * ncell + lin;
+                    atomicOr(&bitmap[b >> 5], 1u << (b & 31));
+                }
+            } else {
+                const auto r0 = load_rec<S>(st, (uint64_t)m0 * estride + off);
+                A val = (A)boosted<S>(r0, v, beaming);
+                if (!single) {
+                    const auto r1 = load_rec<S>(st, (uint64_t)(m0 + 1) * estride + off);
+                    const A b1 = (A)boosted<S>(r1, v, beaming);
+                    val = val + (A)wt * (b1 - val);
+                }
+                const A term = (A)ds * val;
+                if (kahan) {
+                    const A yk = term - comp;
+                    const A tk = sum + yk;
+                    comp = (tk - sum) - yk;
+                    sum = tk;
+                } else {
+                    sum += term;
+                }
+            }
+        }
+        // advance to the neighbour across the nearest face
+        if (sa0 <= sa1 && sa0 <= sa2) {
+            x += stp[0];
+            if ((unsigned)x >= (unsigned)st.n[0]) break;
+            c0++;
+            sb0 = sa0;
+            sa0 = fma((R)c0, dsa[0], base[0]);
+        } else if (sa1 <= sa2) {
+            y += stp[1];
+            if ((unsigned)y >= (unsigned)st.n[1]) break;
+            c1++;
+            sb1 = sa1;
+            sa1 = fma((R)c1, dsa[1], base[1]);
+        } else {
+            z += stp[2];
+            if ((unsigned)z >= (unsigned)st.n[2]) break;
+            c2++;
+            sb2 = sa2;
+            sa2 = fma((R)c2, dsa[2], base[2]);
+        }
+    }
+    nsteps += count;
+    return (double)sum - (double)comp;
+}
+
+// ------------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, double val) {
+    const size_t o = (size_t)pj * v.width + pi;
+    if (v.out_f64) ((double *)v.image)[o] = val;
+    else ((float *)v.image)[o] = (float)val;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Plain kernel: one thread per pixel in row order, one launch per image.
+template <int S, typename R>
+__global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
+                                               unsigned long long *step_acc) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long npix = (long long)v.width * v.height;
+    double val = 0.0;
+    uint32_t ns = 0;
+    if (idx < npix) {
+        const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
+        val = march<S, R, false>(v, pi, pj, nullptr, ns);
+        store_pixel(v, pi, pj, val);
+    }
+    const double fs = wave_sum(val);
+    const uint32_t cs = wave_sum_u32(ns);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&flux_acc[v.acc_index], fs * v.ps * v.ps);
+        atomicAdd(&step_acc[v.acc_index], (unsigned long long)cs);
+    }
+}
+
+// Persistent kernel: every wavefront pulls 64-pixel tiles (tile_w x tile_h)
+// from a queue until all are done.  Tiles are split into n_queues contiguous
+// chunks; a wave starts on chunk (block index mod n_queues), which under
+// round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
+// the other chunks when its own runs dry.
+template <int S, typename R>
+__global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t nq = bl.n_queues;
+    const uint32_t q0 = blockIdx.x % nq;
+    const uint32_t tw_log2 = bl.tile_w_log2;
+    for (uint32_t qi = 0; qi < nq;) {
+        const uint32_t q = (q0 + qi) % nq;
+        const uint32_t begin = (uint32_t)(((uint64_t)bl.n_tiles * q) / nq);
+        const uint32_t end = (uint32_t)(((uint64_t)bl.n_tiles * (q + 1)) / nq);
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(&bl.head[q], 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= end - begin) {
+            qi++;
+            continue;
+        }
+        const Tile tile = bl.tiles[begin + t];
+        const uint32_t vi = __builtin_amdgcn_readfirstlane(tile.view);
+        const RayView &v = bl.views[vi];
+        const int pi = (int)(__builtin_amdgcn_readfirstlane(tile.tx) << tw_log2) +
+                       (lane & ((1 << tw_log2) - 1));
+        const int pj = (int)(__builtin_amdgcn_readfirstlane(tile.ty) << (6 - tw_log2)) +
+                       (lane >> tw_log2);
+        double val = 0.0;
+        uint32_t ns = 0;
+        if (pi < v.width && pj < v.height) {
+            val = march<S, R, false>(v, pi, pj, nullptr, ns);
+            store_pixel(v, pi, pj, val);
+        }
+        const double fs = wave_sum(val);
+        const uint32_t cs = wave_sum_u32(ns);
+        if (lane == 0) {
+            atomicAdd(&bl.flux_acc[v.acc_index], fs * v.ps * v.ps);
+            atomicAdd(&bl.step_acc[v.acc_index], (unsigned long long)cs);
+        }
+    }
+}
+
+// Sample marking for the compulsory-bytes count (untimed instrumentation).
+template <int S, typename R>
+__global__ void __launch_bounds__(256) k_mark(RayView v, uint32_t *bitmap) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long npix = (long long)v.width * v.height;
+    if (idx >= npix) return;
+    uint32_t ns = 0;
+    march<S, R, true>(v, (int)(idx % v.width), (int)(idx / v.width), bitmap, ns);
+}
+
+__global__ void __launch_bounds__(256) k_popcount(const uint32_t *bm, uint64_t words,
+                                                  unsigned long long *out) {
+    unsigned long long c = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        c += __popc(bm[i]);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, c);
+}
+
+__global__ void __launch_bounds__(256) k_fill_u64(unsigned long long *p, uint64_t n,
+                                                  unsigned long long value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void __launch_bounds__(256) k_copy(float4 *__restrict__ dst,
+                                              const float4 *__restrict__ src, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ load / convert
+
+__device__ __forceinline__ uint32_t f2bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ uint32_t f2h_rne(float f) {
+    return (uint32_t)__half_as_ushort(__float2half_rn(f));
+}
+
+// caller layout (one epoch: j [nz][ny][nx], beta [nz][ny][nx][3]) -> resident
+// records, with validation: every value finite, |beta| < 1 in the source type
+// and again after rounding to the storage type.  The first bad element (as
+// epoch * ncell + cell) is kept by atomicMin in *err.
+template <typename Src, int S>
+__global__ void __launch_bounds__(256) k_convert(const Src *__restrict__ j,
+                                                 const Src *__restrict__ beta, int32_t m,
+                                                 StackDev st, void *data,
+                                                 unsigned long long *err) {
+    const uint32_t n0 = st.n[0], n1 = st.n[1];
+    const uint64_t ncell = (uint64_t)n0 * n1 * st.n[2];
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+         c += (uint64_t)gridDim.x * blockDim.x) {
+        const double jv = (double)j[c];
+        const double bx = (double)beta[3 * c], by = (double)beta[3 * c + 1],
+                     bz = (double)beta[3 * c + 2];
+        bool ok = isfinite(jv) && isfinite(bx) && isfinite(by) && isfinite(bz) &&
+                  (bx * bx + by * by + bz * bz) < 1.0;
+        const uint32_t x = (uint32_t)(c % n0), y = (uint32_t)((c / n0) % n1),
+                       z = (uint32_t)(c / ((uint64_t)n0 * n1));
+        const uint64_t rec = (uint64_t)m * st.epoch_stride + cell_offset(st, x, y, z);
+        double qj, qx, qy, qz;
+        if constexpr (S == ST_F64) {
+            double2 *p = (double2 *)data;
+            p[2 * rec] = double2{jv, bx};
+            p[2 * rec + 1] = double2{by, bz};
+            qj = jv; qx = bx; qy = by; qz = bz;
+        } else if constexpr (S == ST_F32) {
+            float4 r{(float)jv, (float)bx, (float)by, (float)bz};
+            ((float4 *)data)[rec] = r;
+            qj = r.x; qx = r.y; qy = r.z; qz = r.w;
+        } else if constexpr (S == ST_F16) {
+            uint32_t hj = f2h_rne((float)jv), hx = f2h_rne((float)bx), hy = f2h_rne((float)by),
+                     hz = f2h_rne((float)bz);
+            ((uint2 *)data)[rec] = uint2{hj | (hx << 16), hy | (hz << 16)};
+            qj = h2f(hj); qx = h2f(hx); qy = h2f(hy); qz = h2f(hz);
+        } else {
+            uint32_t hj = f2bf16_rne((float)jv), hx = f2bf16_rne((float)bx),
+                     hy = f2bf16_rne((float)by), hz = f2bf16_rne((float)bz);
+            ((uint2 *)data)[rec] = uint2{hj | (hx << 16), hy | (hz << 16)};
+            qj = __uint_as_float(hj << 16); qx = __uint_as_float(hx << 16);
+            qy = __uint_as_float(hy << 16); qz = __uint_as_float(hz << 16);
+        }
+        // the stored velocity must stay strictly sub-luminal in the arithmetic
+        // the render uses (FP64, and the FP32 FMA chain of 16-bit stacks)
+        ok = ok && isfinite(qj) && (1.0 - (qx * qx + qy * qy + qz * qz)) > 0.0;
+        if constexpr (S == ST_F16 || S == ST_BF16) {
+            const float fx = (float)qx, fy = (float)qy, fz = (float)qz;
+            ok = ok && fmaf(-fx, fx, fmaf(-fy, fy, fmaf(-fz, fz, 1.0f))) > 0.0f;
+        }
+        if (!ok) atomicMin(err, (unsigned long long)((uint64_t)m * ncell + c));
+    }
+}
+
+template <int RB>
+struct RawRec { uint32_t w[RB / 4]; };
+
+template <int RB>
+__global__ void __launch_bounds__(256) k_rebrick(StackDev from, StackDev to, int32_t m,
+                                                 RawRec<RB> *__restrict__ dst) {
+    const uint32_t n0 = from.n[0], n1 = from.n[1];
+    const uint64_t ncell = (uint64_t)n0 * n1 * from.n[2];
+    const RawRec<RB> *src = (const RawRec<RB> *)from.data;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+         c += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t x = (uint32_t)(c % n0), y = (uint32_t)((c / n0) % n1),
+                       z = (uint32_t)(c / ((uint64_t)n0 * n1));
+        dst[(uint64_t)m * to.epoch_stride + cell_offset(to, x, y, z)] =
+            src[(uint64_t)m * from.epoch_stride + cell_offset(from, x, y, z)];
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned grid_for(uint64_t n, unsigned cap = 1u << 16) {
+    uint64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+template <int S, typename R>
+static hipError_t plain_impl(const RayView &v, double *flux_acc, unsigned long long *step_acc,
+                             hipStream_t s) {
+    const uint64_t npix = (uint64_t)v.width * v.height;
+    hipLaunchKernelGGL((k_plain<S, R>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, v,
+                       flux_acc, step_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *step_acc,
+                        hipStream_t s) {
+    const bool f64 = (v.flags & F_F64_DDA) != 0;
+    switch (v.st.store) {
+        case ST_F64: return plain_impl<ST_F64, double>(v, flux_acc, step_acc, s);
+        case ST_F32: return f64 ? plain_impl<ST_F32, double>(v, flux_acc, step_acc, s)
+                                : plain_impl<ST_F32, float>(v, flux_acc, step_acc, s);
+        case ST_F16: return f64 ? plain_impl<ST_F16, double>(v, flux_acc, step_acc, s)
+                                : plain_impl<ST_F16, float>(v, flux_acc, step_acc, s);
+        case ST_BF16: return f64 ? plain_impl<ST_BF16, double>(v, flux_acc, step_acc, s)
+                                 : plain_impl<ST_BF16, float>(v, flux_acc, step_acc, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int S, typename R>
+static hipError_t batch_impl(const BatchLaunch &bl, int grid_blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_batch<S, R>), dim3((unsigned)grid_blocks), dim3(256), 0, s, bl);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(int store, bool f64, const BatchLaunch &bl, int grid_blocks,
+                        hipStream_t s) {
+    switch (store) {
+        case ST_F64: return batch_impl<ST_F64, double>(bl, grid_blocks, s);
+        case ST_F32: return f64 ? batch_impl<ST_F32, double>(bl, grid_blocks, s)
+                                : batch_impl<ST_F32, float>(bl, grid_blocks, s);
+        case ST_F16: return f64 ? batch_impl<ST_F16, double>(bl, grid_blocks, s)
+                                : batch_impl<ST_F16, float>(bl, grid_blocks, s);
+        case ST_BF16: return f64 ? batch_impl<ST_BF16, double>(bl, grid_blocks, s)
+                                 : batch_impl<ST_BF16, float>(bl, grid_blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int S, typename R>
+static hipError_t mark_impl(const RayView &v, uint32_t *bitmap, hipStream_t s) {
+    const uint64_t npix = (uint64_t)v.width * v.height;
+    hipLaunchKernelGGL((k_mark<S, R>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, v,
+                       bitmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark(const RayView &v, uint32_t *bitmap, hipStream_t s) {
+    const bool f64 = (v.flags & F_F64_DDA) != 0;
+    switch (v.st.store) {
+        case ST_F64: return mark_impl<ST_F64, double>(v, bitmap, s);
+        case ST_F32: return f64 ? mark_impl<ST_F32, double>(v, bitmap, s)
+                                : mark_impl<ST_F32, float>(v, bitmap, s);
+        case ST_F16: return f64 ? mark_impl<ST_F16, double>(v, bitmap, s)
+                                : mark_impl<ST_F16, float>(v, bitmap, s);
+        case ST_BF16: return f64 ? mark_impl<ST_BF16, double>(v, bitmap, s)
+                                 : mark_impl<ST_BF16, float>(v, bitmap, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_popcount(const uint32_t *bitmap, uint64_t words, unsigned long long *out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_popcount, dim3(grid_for(words, 8192)), dim3(256), 0, s, bitmap, words,
+                       out);
+    return hipGetLastError();
+}
+
+template <typename Src, int S>
+static hipError_t convert_impl(const void *j, const void *beta, int32_t m0, int32_t count,
+                               const StackDev &st, void *data, unsigned long long *err,
+                               hipStream_t s) {
+    const uint64_t ncell = (uint64_t)st.n[0] * st.n[1] * st.n[2];
+    const unsigned g = grid_for(ncell, 1u << 15);
+    for (int32_t q = 0; q < count; q++) {
+        hipLaunchKernelGGL((k_convert<Src, S>), dim3(g), dim3(256), 0, s,
+                           (const Src *)j + (size_t)q * ncell,
+                           (const Src *)beta + (size_t)q * ncell * 3, m0 + q, st, data, err);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_convert(int src_f64, int store, const void *j, const void *beta, int32_t m0,
+                          int32_t count, const StackDev &st, void *data,
+                          unsigned long long *err, hipStream_t s) {
+    if (src_f64) {
+        switch (store) {
+            case ST_F64: return convert_impl<double, ST_F64>(j, beta, m0, count, st, data, err, s);
+            case ST_F32: return convert_impl<double, ST_F32>(j, beta, m0, count, st, data, err, s);
+            case ST_F16: return convert_impl<double, ST_F16>(j, beta, m0, count, st, data, err, s);
+            case ST_BF16: return convert_impl<double, ST_BF16>(j, beta, m0, count, st, data, err, s);
+        }
+    } else {
+        switch (store) {
+            case ST_F64: return convert_impl<float, ST_F64>(j, beta, m0, count, st, data, err, s);
+            case ST_F32: return convert_impl<float, ST_F32>(j, beta, m0, count, st, data, err, s);
+            case ST_F16: return convert_impl<float, ST_F16>(j, beta, m0, count, st, data, err, s);
+            case ST_BF16: return convert_impl<float, ST_BF16>(j, beta, m0, count, st, data, err, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int RB>
+static hipError_t rebrick_impl(const StackDev &from, const StackDev &to, void *dst,
+                               hipStream_t s) {
+    const uint64_t ncell = (uint64_t)from.n[0] * from.n[1] * from.n[2];
+    for (int32_t m = 0; m < from.n_epochs; m++) {
+        hipLaunchKernelGGL((k_rebrick<RB>), dim3(grid_for(ncell, 1u << 15)), dim3(256), 0, s,
+                           from, to, m, (RawRec<RB> *)dst);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_rebrick(int store, const StackDev &from, const StackDev &to, void *dst,
+                          hipStream_t s) {
+    switch (store) {
+        case ST_F64: return rebrick_impl<32>(from, to, dst, s);
+        case ST_F32: return rebrick_impl<16>(from, to, dst, s);
+        case ST_F16:
+        case ST_BF16: return rebrick_impl<8>(from, to, dst, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 4096)), dim3(256), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s) {
+    const uint64_t n = bytes / 16;
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 1u << 14)), dim3(256), 0, s, (float4 *)dst,
+                       (const float4 *)src, n);
+    return hipGetLastError();
+}
+
+}  // namespace dart

@@ -1,0 +1,85 @@
+// dart_runtime.h -- host-side objects shared by the runtime and the server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "../../include/dart.h"
+#include "dart_internal.h"
+
+struct dart_stack {
+    dart::StackDev dev{};
+    dart_dtype storage = DART_F32;
+    std::vector<double> times;
+    std::vector<char> filled;
+    uint64_t bytes = 0;
+    uint64_t generation = 0;  // bumped whenever the resident layout or data change
+    int device = 0;
+    dart_tuning tuning{8, 8, 16, 0};
+    bool tuned = false;
+    std::mutex mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;  // last render per stream
+    std::atomic<int> pinned{0};                            // server requests holding the stack
+};
+
+namespace dart {
+
+dart_status fail(dart_status st, const char *fmt, ...);
+dart_status hip_fail(hipError_t e, const char *what);
+int device_cus(int dev);
+uint32_t record_bytes(int store);
+dart_status resolve_view(const dart_stack *s, const dart_view *v, RayView *rv);
+void note_use(const dart_stack *s, hipStream_t stream);
+bool stack_busy(const dart_stack *s);
+dart_tuning tuning_for(const dart_stack *s);
+
+// One launch group of a batch: views of one storage type and ray precision.
+struct Group {
+    int store = 0;
+    bool f64 = false;
+    std::vector<RayView> views;
+    std::vector<Tile> tiles;
+    size_t view_off = 0, tile_off = 0;  // offsets in the uploaded descriptor arrays
+    uint32_t tile_w_log2 = 3;
+    uint32_t n_queues = 8;
+};
+
+dart_status plan_batch(const dart_stack *const *stacks, const dart_view *views, int32_t n,
+                       void *const *images, const dart_tuning &tun, std::vector<Group> &groups);
+
+// Per-(device, stream) scratch: accumulators, descriptor arrays, image staging,
+// pinned upload staging and the last captured batch graph.
+struct Workspace {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::mutex mu;
+    unsigned long long *acc = nullptr;  // flux[n] (as double bits), steps[n], queue heads
+    size_t acc_cap = 0;
+    RayView *views = nullptr;
+    size_t views_cap = 0;
+    Tile *tiles = nullptr;
+    size_t tiles_cap = 0;
+    unsigned long long *img = nullptr;  // staging for host-destined images
+    size_t img_cap = 0;
+    void *stage = nullptr;              // pinned host staging for descriptor uploads
+    size_t stage_cap = 0;
+    hipEvent_t stage_done{};
+    bool stage_ready = false;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint8_t> graph_key;
+};
+
+Workspace *get_workspace(hipStream_t stream);
+hipError_t ws_reserve(Workspace *ws, size_t n_views, size_t n_tiles, size_t img_u64,
+                      size_t n_queue_slots);
+hipError_t enqueue_plan(const std::vector<Group> &groups, int32_t n, unsigned long long *acc,
+                        const RayView *dviews, const Tile *dtiles, const dart_tuning &tun,
+                        int device, hipStream_t stream);
+void assign_offsets(std::vector<Group> &groups, size_t *n_views, size_t *n_tiles);
+void pack_descriptors(const std::vector<Group> &groups, size_t n_views, void *dst);
+
+}  // namespace dart

@@ -1,0 +1,980 @@
+// dart_runtime.hip -- host runtime behind the C ABI (include/dart.h):
+// resident stacks, view resolution, the plain and batched render paths
+// (planner, tile queue, hipGraph replay), tuning, sample counting and the
+// bandwidth probe.  The render server lives in dart_server.hip.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <chrono>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dart.h"
+#include "dart_internal.h"
+#include "dart_runtime.h"
+
+using namespace dart;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+dart_status dart::fail(dart_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+dart_status dart::hip_fail(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(DART_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(DART_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char *dart_last_error(void) { return g_err.c_str(); }
+extern "C" const char *dart_version(void) { return "dart-mi355x 0.1 (gfx950)"; }
+
+#define HIP_TRY(call, what)                         \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// ------------------------------------------------------------------ devices
+
+int dart::device_cus(int dev) {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    cache[dev] = cus;
+    return cus;
+}
+
+// ------------------------------------------------------------------ stacks
+
+static int store_of(dart_dtype d) {
+    switch (d) {
+        case DART_F64: return ST_F64;
+        case DART_F32: return ST_F32;
+        case DART_F16: return ST_F16;
+        case DART_BF16: return ST_BF16;
+    }
+    return -1;
+}
+uint32_t dart::record_bytes(int store) {
+    return store == ST_F64 ? 32u : store == ST_F32 ? 16u : 8u;
+}
+
+static int ilog2_exact(int v) {
+    int l = 0;
+    while ((1 << l) < v) l++;
+    return (1 << l) == v ? l : -1;
+}
+
+static void layout(dart_stack *s, const int lb[3]) {
+    uint64_t per = 1;
+    for (int a = 0; a < 3; a++) {
+        s->dev.lb[a] = lb[a];
+        s->dev.nb[a] = (s->dev.n[a] + (1 << lb[a]) - 1) >> lb[a];
+        per *= (uint64_t)s->dev.nb[a] << lb[a];
+    }
+    s->dev.epoch_stride = per;
+}
+
+static void default_brick(int store, int lb[3]) {
+    // 4x4x4 cells: 512 B (16-bit) to 2 KB (FP64) per brick, several 128-B lines
+    (void)store;
+    lb[0] = lb[1] = lb[2] = 2;
+}
+
+static dart_status check_geometry(const int32_t dims[3], const double cell[3], int32_t M,
+                                  const double *times) {
+    if (!dims || !cell || !times) return fail(DART_E_INVAL, "null dims/cell/epoch_times");
+    for (int a = 0; a < 3; a++) {
+        if (dims[a] < 1 || dims[a] > (1 << 20))
+            return fail(DART_E_INVAL, "dims[%d]=%d out of range", a, dims[a]);
+        if (!(cell[a] > 0.0) || !isfinite(cell[a]))
+            return fail(DART_E_INVAL, "cell[%d]=%g must be finite and > 0", a, cell[a]);
+    }
+    const uint64_t ncell = (uint64_t)dims[0] * dims[1] * dims[2];
+    if (ncell > (1ull << 31)) return fail(DART_E_INVAL, "more than 2^31 cells per epoch");
+    if (M < 1 || M > 65536) return fail(DART_E_INVAL, "n_epochs=%d out of range", M);
+    for (int m = 0; m < M; m++)
+        if (!isfinite(times[m])) return fail(DART_E_INVAL, "epoch_times[%d] not finite", m);
+    for (int m = 0; m + 1 < M; m++)
+        if (!(times[m + 1] > times[m]))
+            return fail(DART_E_INVAL, "epoch_times not strictly increasing at %d", m + 1);
+    return DART_OK;
+}
+
+extern "C" dart_status dart_stack_create(const int32_t dims[3], const double cell[3],
+                                         int32_t n_epochs, const double *epoch_times,
+                                         dart_dtype storage, uint32_t flags, dart_stack **out) {
+    (void)flags;
+    if (!out) return fail(DART_E_INVAL, "out is NULL");
+    *out = nullptr;
+    dart_status st = check_geometry(dims, cell, n_epochs, epoch_times);
+    if (st != DART_OK) return st;
+    const int store = store_of(storage);
+    if (store < 0) return fail(DART_E_INVAL, "unknown storage dtype %d", (int)storage);
+    std::unique_ptr<dart_stack> s(new dart_stack());
+    HIP_TRY(hipGetDevice(&s->device), "hipGetDevice");
+    for (int a = 0; a < 3; a++) {
+        s->dev.n[a] = dims[a];
+        s->dev.cell[a] = cell[a];
+    }
+    s->dev.n_epochs = n_epochs;
+    s->dev.store = store;
+    s->storage = storage;
+    s->times.assign(epoch_times, epoch_times + n_epochs);
+    s->filled.assign(n_epochs, 0);
+    int lb[3];
+    default_brick(store, lb);
+    layout(s.get(), lb);
+    s->bytes = s->dev.epoch_stride * n_epochs * record_bytes(store);
+    void *data = nullptr, *t = nullptr;
+    hipError_t e = hipMalloc(&data, s->bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(stack)");
+    e = hipMalloc(&t, sizeof(double) * n_epochs);
+    if (e != hipSuccess) {
+        (void)hipFree(data);
+        return hip_fail(e, "hipMalloc(times)");
+    }
+    e = hipMemcpy(t, epoch_times, sizeof(double) * n_epochs, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(data);
+        (void)hipFree(t);
+        return hip_fail(e, "hipMemcpy(times)");
+    }
+    s->dev.data = data;
+    s->dev.times = (const double *)t;
+    *out = s.release();
+    return DART_OK;
+}
+
+static dart_status set_epochs_impl(dart_stack *s, int32_t m0, int32_t count, dart_dtype src,
+                                   const void *j, const void *beta, uint32_t flags,
+                                   hipStream_t stream) {
+    if (!s) return fail(DART_E_INVAL, "stack is NULL");
+    if (!j || !beta) return fail(DART_E_INVAL, "emissivity/velocity is NULL");
+    if (m0 < 0 || count < 1 || m0 + count > s->dev.n_epochs)
+        return fail(DART_E_INVAL, "epoch range [%d, %d) outside [0, %d)", m0, m0 + count,
+                    s->dev.n_epochs);
+    if (src != DART_F64 && src != DART_F32)
+        return fail(DART_E_INVAL, "src_dtype must be DART_F64 or DART_F32");
+    const int src_f64 = src == DART_F64;
+    const size_t esz = src_f64 ? 8 : 4;
+    const uint64_t ncell = (uint64_t)s->dev.n[0] * s->dev.n[1] * s->dev.n[2];
+    unsigned long long *err = nullptr;
+    HIP_TRY(hipMalloc(&err, sizeof(unsigned long long)), "hipMalloc(err)");
+    struct Guard {
+        void *p[3] = {nullptr, nullptr, nullptr};
+        ~Guard() { for (void *q : p) if (q) (void)hipFree(q); }
+    } guard;
+    guard.p[0] = err;
+    hipError_t e = launch_fill_u64(err, 1, ~0ull, stream);
+    if (e != hipSuccess) return hip_fail(e, "clear error flag");
+    if (flags & F_DEVICE_PTRS) {
+        e = launch_convert(src_f64, s->dev.store, j, beta, m0, count, s->dev, (void *)s->dev.data,
+                           err, stream);
+        if (e != hipSuccess) return hip_fail(e, "convert kernel");
+    } else {
+        // host arrays: one epoch at a time through device staging
+        void *dj = nullptr, *db = nullptr;
+        HIP_TRY(hipMalloc(&dj, ncell * esz), "hipMalloc(staging)");
+        guard.p[1] = dj;
+        HIP_TRY(hipMalloc(&db, ncell * esz * 3), "hipMalloc(staging)");
+        guard.p[2] = db;
+        for (int32_t q = 0; q < count; q++) {
+            const char *hj = (const char *)j + (size_t)q * ncell * esz;
+            const char *hb = (const char *)beta + (size_t)q * ncell * esz * 3;
+            HIP_TRY(hipMemcpyAsync(dj, hj, ncell * esz, hipMemcpyHostToDevice, stream), "H2D j");
+            HIP_TRY(hipMemcpyAsync(db, hb, ncell * esz * 3, hipMemcpyHostToDevice, stream),
+                    "H2D beta");
+            e = launch_convert(src_f64, s->dev.store, dj, db, m0 + q, 1, s->dev,
+                               (void *)s->dev.data, err, stream);
+            if (e != hipSuccess) return hip_fail(e, "convert kernel");
+            HIP_TRY(hipStreamSynchronize(stream), "sync");
+        }
+    }
+    unsigned long long bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, err, sizeof(bad), hipMemcpyDeviceToHost, stream), "D2H err");
+    HIP_TRY(hipStreamSynchronize(stream), "sync");
+    if (bad != ~0ull) {
+        const uint64_t m = bad / ncell, c = bad % ncell;
+        const uint64_t x = c % s->dev.n[0], y = (c / s->dev.n[0]) % s->dev.n[1],
+                       z = c / ((uint64_t)s->dev.n[0] * s->dev.n[1]);
+        return fail(DART_E_RANGE,
+                    "non-finite value or |beta| >= 1 (in the source or after rounding to the "
+                    "storage type) at epoch %llu, cell (x=%llu, y=%llu, z=%llu)",
+                    (unsigned long long)m, (unsigned long long)x, (unsigned long long)y,
+                    (unsigned long long)z);
+    }
+    for (int32_t q = 0; q < count; q++) s->filled[m0 + q] = 1;
+    s->generation++;
+    return DART_OK;
+}
+
+extern "C" dart_status dart_stack_set_epochs(dart_stack *s, int32_t m0, int32_t count,
+                                             dart_dtype src_dtype, const void *emissivity,
+                                             const void *velocity, uint32_t flags,
+                                             void *hip_stream) {
+    return set_epochs_impl(s, m0, count, src_dtype, emissivity, velocity, flags,
+                           (hipStream_t)hip_stream);
+}
+
+extern "C" dart_status dart_load_epochs(const int32_t dims[3], const double cell[3],
+                                        int32_t n_epochs, const double *epoch_times,
+                                        dart_dtype src_dtype, dart_dtype storage,
+                                        const void *emissivity, const void *velocity,
+                                        uint32_t flags, void *hip_stream, dart_stack **out) {
+    if (!out) return fail(DART_E_INVAL, "out is NULL");
+    *out = nullptr;
+    dart_stack *s = nullptr;
+    dart_status st = dart_stack_create(dims, cell, n_epochs, epoch_times, storage, flags, &s);
+    if (st != DART_OK) return st;
+    st = set_epochs_impl(s, 0, n_epochs, src_dtype, emissivity, velocity, flags,
+                         (hipStream_t)hip_stream);
+    if (st != DART_OK) {
+        std::string keep = g_err;
+        (void)hipFree((void *)s->dev.data);
+        (void)hipFree((void *)s->dev.times);
+        delete s;
+        g_err = keep;
+        return st;
+    }
+    *out = s;
+    return DART_OK;
+}
+
+void dart::note_use(const dart_stack *cs, hipStream_t stream) {
+    dart_stack *s = const_cast<dart_stack *>(cs);
+    std::lock_guard<std::mutex> g(s->mu);
+    for (auto &u : s->uses)
+        if (u.first == stream) {
+            (void)hipEventRecord(u.second, stream);
+            return;
+        }
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return;
+    (void)hipEventRecord(ev, stream);
+    s->uses.emplace_back(stream, ev);
+}
+
+bool dart::stack_busy(const dart_stack *cs) {
+    dart_stack *s = const_cast<dart_stack *>(cs);
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->pinned.load() > 0) return true;
+    for (auto &u : s->uses)
+        if (hipEventQuery(u.second) == hipErrorNotReady) return true;
+    return false;
+}
+
+extern "C" dart_status dart_free_epochs(dart_stack *s) {
+    if (!s) return fail(DART_E_INVAL, "stack is NULL");
+    if (stack_busy(s)) return fail(DART_E_BUSY, "renders that read this stack are in flight");
+    for (auto &u : s->uses) (void)hipEventDestroy(u.second);
+    (void)hipFree((void *)s->dev.data);
+    (void)hipFree((void *)s->dev.times);
+    delete s;
+    return DART_OK;
+}
+
+extern "C" dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info *info) {
+    if (!s || !info) return fail(DART_E_INVAL, "NULL argument");
+    for (int a = 0; a < 3; a++) {
+        info->dims[a] = s->dev.n[a];
+        info->brick[a] = 1 << s->dev.lb[a];
+    }
+    info->n_epochs = s->dev.n_epochs;
+    info->storage = s->storage;
+    info->device_bytes = s->bytes;
+    return DART_OK;
+}
+
+extern "C" dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_out) {
+    if (!s || !bytes_out) return fail(DART_E_INVAL, "NULL argument");
+    *bytes_out = record_bytes(s->dev.store);
+    return DART_OK;
+}
+
+extern "C" dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3],
+                                          void *hip_stream) {
+    if (!s || !brick) return fail(DART_E_INVAL, "NULL argument");
+    int lb[3], cells = 1;
+    for (int a = 0; a < 3; a++) {
+        lb[a] = ilog2_exact(brick[a]);
+        if (lb[a] < 0 || brick[a] > 16) return fail(DART_E_INVAL, "brick[%d]=%d", a, brick[a]);
+        cells *= brick[a];
+    }
+    if (cells > 4096) return fail(DART_E_INVAL, "brick larger than 4096 cells");
+    if (stack_busy(s)) return fail(DART_E_BUSY, "renders that read this stack are in flight");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    dart_stack tmp;
+    tmp.dev = s->dev;
+    layout(&tmp, lb);
+    const uint64_t bytes = tmp.dev.epoch_stride * s->dev.n_epochs * record_bytes(s->dev.store);
+    void *data = nullptr;
+    HIP_TRY(hipMalloc(&data, bytes), "hipMalloc(rebrick)");
+    tmp.dev.data = data;
+    hipError_t e = launch_rebrick(s->dev.store, s->dev, tmp.dev, data, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        (void)hipFree(data);
+        return hip_fail(e, "rebrick");
+    }
+    (void)hipFree((void *)s->dev.data);
+    s->dev = tmp.dev;
+    s->bytes = bytes;
+    s->generation++;
+    return DART_OK;
+}
+
+// ------------------------------------------------------------------ views
+
+static void sincos_deg(double deg, double *s, double *c) {
+    double r = fmod(deg, 360.0);
+    if (r < 0) r += 360.0;
+    if (r == 0.0) { *s = 0.0; *c = 1.0; return; }
+    if (r == 90.0) { *s = 1.0; *c = 0.0; return; }
+    if (r == 180.0) { *s = 0.0; *c = -1.0; return; }
+    if (r == 270.0) { *s = -1.0; *c = 0.0; return; }
+    *s = sin(deg * (M_PI / 180.0));
+    *c = cos(deg * (M_PI / 180.0));
+}
+
+dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView *rv) {
+    if (!s || !v || !rv) return fail(DART_E_INVAL, "NULL stack or view");
+    for (int32_t m = 0; m < s->dev.n_epochs; m++)
+        if (!s->filled[m]) return fail(DART_E_INVAL, "epoch %d of the stack was never filled", m);
+    if (v->width < 1 || v->height < 1 || (int64_t)v->width * v->height > (1ll << 31))
+        return fail(DART_E_INVAL, "image %dx%d out of range", v->width, v->height);
+    if (v->width > 65535 * 64 || v->height > 65535 * 64)
+        return fail(DART_E_INVAL, "image side too large");
+    if (!(v->pixel_scale > 0.0) || !isfinite(v->pixel_scale))
+        return fail(DART_E_INVAL, "pixel_scale must be finite and > 0");
+    if (!isfinite(v->theta_deg) || !isfinite(v->phi_deg) || !isfinite(v->t_obs) ||
+        !isfinite(v->alpha))
+        return fail(DART_E_INVAL, "theta, phi, t_obs and alpha must be finite");
+    if (v->out_dtype != DART_F32 && v->out_dtype != DART_F64)
+        return fail(DART_E_INVAL, "out_dtype must be DART_F32 or DART_F64");
+    if (v->out_dtype == DART_F64 && s->storage != DART_F64)
+        return fail(DART_E_INVAL, "FP64 images need an FP64 stack");
+    if (v->flags & ~(uint32_t)(DART_NO_LOOKBACK | DART_NO_BEAMING | DART_NEAREST_EPOCH |
+                               DART_NO_KAHAN | DART_FORCE_F64_DDA | DART_DEVICE_PTRS))
+        return fail(DART_E_INVAL, "unknown view flags 0x%x", v->flags);
+    memset(rv, 0, sizeof(*rv));
+    double st, ct, sp, cp;
+    sincos_deg(v->theta_deg, &st, &ct);
+    sincos_deg(v->phi_deg, &sp, &cp);
+    const double nhat[3] = {st * cp, st * sp, ct};
+    for (int a = 0; a < 3; a++) {
+        rv->shat[a] = -nhat[a];
+        rv->centre[a] = 0.5 * s->dev.n[a] * s->dev.cell[a];
+    }
+    rv->eu[0] = -sp; rv->eu[1] = cp; rv->eu[2] = 0.0;
+    rv->ev[0] = -ct * cp; rv->ev[1] = -ct * sp; rv->ev[2] = st;
+    rv->ps = v->pixel_scale;
+    rv->t_obs = v->t_obs;
+    rv->p = 2.0 + v->alpha;
+    rv->flags = v->flags & (F_NO_LOOKBACK | F_NO_BEAMING | F_NEAREST | F_NO_KAHAN | F_F64_DDA);
+    // long rays: FP64 ray parameters when a ray may cross more than ~4k cells
+    if (s->dev.n[0] + s->dev.n[1] + s->dev.n[2] > 4096) rv->flags |= F_F64_DDA;
+    rv->width = v->width;
+    rv->height = v->height;
+    rv->out_f64 = v->out_dtype == DART_F64;
+    rv->st = s->dev;
+    const std::vector<double> &t = s->times;
+    const int M = (int)t.size();
+    if (v->flags & DART_NO_LOOKBACK) {
+        rv->s_lo = -INFINITY;
+        rv->s_hi = INFINITY;
+        if (v->t_obs >= t[0] && v->t_obs <= t[M - 1]) {
+            int m = 0;
+            while (m + 1 < M - 1 && t[m + 1] <= v->t_obs) m++;
+            rv->fixed_m = m;
+            rv->fixed_w = M >= 2 ? (v->t_obs - t[m]) / (t[m + 1] - t[m]) : 0.0;
+        } else {
+            rv->fixed_m = -1;
+        }
+    } else {
+        rv->s_lo = v->t_obs - t[M - 1];
+        rv->s_hi = v->t_obs - t[0];
+        rv->fixed_m = 0;
+    }
+    return DART_OK;
+}
+
+// ------------------------------------------------------------------ workspaces
+
+Workspace *dart::get_workspace(hipStream_t stream) {
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> all;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(mu);
+    auto &slot = all[{dev, stream}];
+    if (!slot) {
+        slot.reset(new Workspace());
+        slot->stream = stream;
+        slot->device = dev;
+    }
+    return slot.get();
+}
+
+template <typename T>
+static hipError_t grow_dev(T *&p, size_t &cap, size_t need) {
+    if (need <= cap && p) return hipSuccess;
+    if (p) {
+        hipError_t e = hipFree(p);
+        if (e != hipSuccess) return e;
+        p = nullptr;
+        cap = 0;
+    }
+    size_t n = std::max(need, (size_t)1);
+    hipError_t e = hipMalloc((void **)&p, n * sizeof(T));
+    if (e == hipSuccess) cap = n;
+    return e;
+}
+
+static hipError_t grow_host(void *&p, size_t &cap, size_t need) {
+    if (need <= cap && p) return hipSuccess;
+    if (p) {
+        (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    hipError_t e = hipHostMalloc(&p, std::max(need, (size_t)64), hipHostMallocDefault);
+    if (e == hipSuccess) cap = std::max(need, (size_t)64);
+    return e;
+}
+
+static void drop_graph(Workspace *ws) {
+    if (ws->graph_exec) (void)hipGraphExecDestroy(ws->graph_exec);
+    ws->graph_exec = nullptr;
+    ws->graph_key.clear();
+}
+
+hipError_t dart::ws_reserve(Workspace *ws, size_t n_views, size_t n_tiles, size_t img_bytes,
+                            size_t n_queues) {
+    hipError_t e;
+    // a captured graph holds these pointers: any reallocation invalidates it
+    const void *before[4] = {ws->acc, ws->views, ws->tiles, ws->img};
+    if (ws->stage_ready) {
+        e = hipEventSynchronize(ws->stage_done);
+        if (e != hipSuccess) return e;
+    }
+    if ((e = grow_dev(ws->acc, ws->acc_cap, 2 * std::max(n_views, (size_t)1) + n_queues)) != hipSuccess)
+        return e;
+    if ((e = grow_dev(ws->views, ws->views_cap, std::max(n_views, (size_t)1))) != hipSuccess) return e;
+    if ((e = grow_dev(ws->tiles, ws->tiles_cap, std::max(n_tiles, (size_t)1))) != hipSuccess) return e;
+    if (img_bytes && (e = grow_dev(ws->img, ws->img_cap, img_bytes)) != hipSuccess) return e;
+    const size_t stage = n_views * sizeof(RayView) + n_tiles * sizeof(Tile) + 64;
+    if ((e = grow_host(ws->stage, ws->stage_cap, stage)) != hipSuccess) return e;
+    if (!ws->stage_ready) {
+        if ((e = hipEventCreateWithFlags(&ws->stage_done, hipEventDisableTiming)) != hipSuccess)
+            return e;
+        ws->stage_ready = true;
+    }
+    const void *after[4] = {ws->acc, ws->views, ws->tiles, ws->img};
+    if (memcmp(before, after, sizeof(before)) != 0) drop_graph(ws);
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ plain render
+
+extern "C" dart_status dart_render(const dart_stack *s, const dart_view *v, void *image,
+                                   double *flux_out, uint64_t *steps_out, void *hip_stream) {
+    if (!image) return fail(DART_E_INVAL, "image is NULL");
+    RayView rv;
+    dart_status st = resolve_view(s, v, &rv);
+    if (st != DART_OK) return st;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    Workspace *ws = get_workspace(stream);
+    std::lock_guard<std::mutex> g(ws->mu);
+    const bool dev_img = (v->flags & DART_DEVICE_PTRS) != 0;
+    const size_t img_bytes = (size_t)v->width * v->height * (rv.out_f64 ? 8 : 4);
+    HIP_TRY(ws_reserve(ws, 1, 0, dev_img ? 0 : img_bytes / 8 + 1, 0), "workspace");
+    rv.image = dev_img ? image : (void *)ws->img;
+    rv.acc_index = 0;
+    double *flux_acc = (double *)ws->acc;
+    unsigned long long *step_acc = ws->acc + 1;
+    HIP_TRY(launch_fill_u64(ws->acc, 2, 0ull, stream), "clear accumulators");
+    HIP_TRY(launch_plain(rv, flux_acc, step_acc, stream), "render kernel");
+    note_use(s, stream);
+    if (!dev_img)
+        HIP_TRY(hipMemcpyAsync(image, ws->img, img_bytes, hipMemcpyDeviceToHost, stream), "D2H image");
+    if (flux_out || steps_out || !dev_img) {
+        unsigned long long acc[2];
+        HIP_TRY(hipMemcpyAsync(acc, ws->acc, sizeof(acc), hipMemcpyDeviceToHost, stream), "D2H acc");
+        HIP_TRY(hipStreamSynchronize(stream), "sync");
+        double f;
+        memcpy(&f, &acc[0], sizeof(f));
+        if (flux_out) *flux_out = f;
+        if (steps_out) *steps_out = acc[1];
+    }
+    return DART_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+
+static std::mutex g_tune_mu;
+static dart_tuning g_tuning = {8, 8, 16, 0};
+
+static dart_status check_tuning(const dart_tuning *t) {
+    if (!t) return fail(DART_E_INVAL, "tuning is NULL");
+    const int lw = ilog2_exact(t->tile_w), lh = ilog2_exact(t->tile_h);
+    if (lw < 0 || lh < 0 || t->tile_w * t->tile_h != 64)
+        return fail(DART_E_INVAL, "tile %dx%d must be powers of two with 64 pixels", t->tile_w,
+                    t->tile_h);
+    if (t->waves_per_cu < 4 || t->waves_per_cu > 64 || t->waves_per_cu % 4)
+        return fail(DART_E_INVAL, "waves_per_cu must be a multiple of 4 in [4, 64]");
+    if (t->order != 0 && t->order != 1) return fail(DART_E_INVAL, "order must be 0 or 1");
+    return DART_OK;
+}
+
+extern "C" dart_status dart_set_tuning(const dart_tuning *t) {
+    dart_status st = check_tuning(t);
+    if (st != DART_OK) return st;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuning = *t;
+    return DART_OK;
+}
+
+extern "C" dart_status dart_get_tuning(dart_tuning *t) {
+    if (!t) return fail(DART_E_INVAL, "tuning is NULL");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    *t = g_tuning;
+    return DART_OK;
+}
+
+dart_tuning dart::tuning_for(const dart_stack *s) {
+    if (s && s->tuned) return s->tuning;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return g_tuning;
+}
+
+// ------------------------------------------------------------------ batch planner
+
+// Estimated cell-steps of the ray through the tile centre, times 64 rays.
+static double tile_cost(const RayView &rv, int tx, int ty, int tw, int th) {
+    const double u = ((tx + 0.5) * tw - 0.5 * rv.width) * rv.ps;
+    const double w = ((ty + 0.5) * th - 0.5 * rv.height) * rv.ps;
+    double s_in = -INFINITY, s_out = INFINITY, per_len = 0.0;
+    for (int a = 0; a < 3; a++) {
+        const double o = rv.centre[a] + u * rv.eu[a] + w * rv.ev[a];
+        const double d = rv.shat[a], hi = rv.st.n[a] * rv.st.cell[a];
+        per_len += fabs(d) / rv.st.cell[a];
+        if (d == 0.0) {
+            if (o < 0 || o >= hi) return 1.0;
+            continue;
+        }
+        double t0 = -o / d, t1 = (hi - o) / d;
+        s_in = std::max(s_in, std::min(t0, t1));
+        s_out = std::min(s_out, std::max(t0, t1));
+    }
+    s_in = std::max(s_in, rv.s_lo);
+    s_out = std::min(s_out, rv.s_hi);
+    if (!(s_out > s_in)) return 1.0;
+    return 1.0 + 64.0 * (s_out - s_in) * per_len;
+}
+
+dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *views, int32_t n,
+                             void *const *images, const dart_tuning &tun,
+                             std::vector<Group> &groups) {
+    groups.clear();
+    const int lw = ilog2_exact(tun.tile_w);
+    const int tw = tun.tile_w, th = tun.tile_h;
+    std::map<int, size_t> gindex;
+    for (int32_t i = 0; i < n; i++) {
+        RayView rv;
+        dart_status st = resolve_view(stacks[i], &views[i], &rv);
+        if (st != DART_OK) return fail(st, "view %d: %s", i, dart_last_error());
+        if (!images[i]) return fail(DART_E_INVAL, "images[%d] is NULL", i);
+        rv.image = images[i];
+        rv.acc_index = i;
+        const int key = rv.st.store * 2 + ((rv.flags & F_F64_DDA) ? 1 : 0);
+        auto it = gindex.find(key);
+        if (it == gindex.end()) {
+            it = gindex.emplace(key, groups.size()).first;
+            groups.emplace_back();
+            groups.back().store = rv.st.store;
+            groups.back().f64 = (rv.flags & F_F64_DDA) != 0;
+        }
+        Group &g = groups[it->second];
+        const uint32_t vi = (uint32_t)g.views.size();
+        g.views.push_back(rv);
+        const int ntx = (rv.width + tw - 1) / tw, nty = (rv.height + th - 1) / th;
+        for (int ty = 0; ty < nty; ty++)
+            for (int tx = 0; tx < ntx; tx++) {
+                Tile t;
+                t.view = vi;
+                t.tx = (uint16_t)tx;
+                t.ty = (uint16_t)ty;
+                g.tiles.push_back(t);
+            }
+    }
+    for (Group &g : groups) {
+        g.tile_w_log2 = (uint32_t)lw;
+        if (tun.order == 1) {
+            // longest estimated tile first; the queue chunks interleave so each
+            // XCD's chunk also runs longest first
+            std::vector<std::pair<double, uint32_t>> cost(g.tiles.size());
+            for (size_t k = 0; k < g.tiles.size(); k++) {
+                const Tile &t = g.tiles[k];
+                cost[k] = {tile_cost(g.views[t.view], t.tx, t.ty, tw, th), (uint32_t)k};
+            }
+            std::stable_sort(cost.begin(), cost.end(),
+                             [](const std::pair<double, uint32_t> &a,
+                                const std::pair<double, uint32_t> &b) { return a.first > b.first; });
+            const size_t nt = g.tiles.size(), nq = 8;
+            std::vector<Tile> out(nt);
+            // rank r goes to chunk r % nq, position r / nq inside it
+            std::vector<size_t> chunk_begin(nq + 1);
+            for (size_t q = 0; q <= nq; q++) chunk_begin[q] = nt * q / nq;
+            std::vector<size_t> fill(nq, 0);
+            size_t q = 0;
+            for (size_t r = 0; r < nt; r++) {
+                // next chunk with room, round robin
+                for (size_t tries = 0; tries < nq; tries++) {
+                    if (chunk_begin[q] + fill[q] < chunk_begin[q + 1]) break;
+                    q = (q + 1) % nq;
+                }
+                out[chunk_begin[q] + fill[q]++] = g.tiles[cost[r].second];
+                q = (q + 1) % nq;
+            }
+            g.tiles.swap(out);
+        }
+        g.n_queues = 8;
+    }
+    return DART_OK;
+}
+
+// Enqueues clear + persistent kernels of every group.  Accumulator layout:
+// flux[n] (double bits), steps[n], then 4 slots (8 x uint32 queue heads) per
+// group; dviews / dtiles hold the groups' descriptors at their offsets.
+hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
+                              unsigned long long *acc, const RayView *dviews, const Tile *dtiles,
+                              const dart_tuning &tun, int device, hipStream_t stream) {
+    hipError_t e = launch_fill_u64(acc, 2 * (size_t)n + 4 * groups.size(), 0ull, stream);
+    if (e != hipSuccess) return e;
+    const int cus = device_cus(device);
+    const int blocks = std::max(1, cus * tun.waves_per_cu / 4);
+    for (size_t gi = 0; gi < groups.size(); gi++) {
+        const Group &g = groups[gi];
+        BatchLaunch bl;
+        bl.views = dviews + g.view_off;
+        bl.tiles = dtiles + g.tile_off;
+        bl.n_tiles = (uint32_t)g.tiles.size();
+        bl.head = (uint32_t *)(acc + 2 * (size_t)n + 4 * gi);
+        bl.n_queues = g.n_queues;
+        bl.tile_w_log2 = g.tile_w_log2;
+        bl.flux_acc = (double *)acc;
+        bl.step_acc = acc + n;
+        e = launch_batch(g.store, g.f64, bl, blocks, stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void dart::assign_offsets(std::vector<Group> &groups, size_t *n_views, size_t *n_tiles) {
+    size_t nv = 0, nt = 0;
+    for (Group &gr : groups) {
+        gr.view_off = nv;
+        gr.tile_off = nt;
+        nv += gr.views.size();
+        nt += gr.tiles.size();
+    }
+    *n_views = nv;
+    *n_tiles = nt;
+}
+
+void dart::pack_descriptors(const std::vector<Group> &groups, size_t n_views, void *dst) {
+    char *h = (char *)dst;
+    char *ht = h + n_views * sizeof(RayView);
+    for (const Group &gr : groups) {
+        memcpy(h + gr.view_off * sizeof(RayView), gr.views.data(), gr.views.size() * sizeof(RayView));
+        memcpy(ht + gr.tile_off * sizeof(Tile), gr.tiles.data(), gr.tiles.size() * sizeof(Tile));
+    }
+}
+
+extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const dart_view *views,
+                                         int32_t n, void *const *images, double *flux_out,
+                                         uint64_t *steps_out, void *hip_stream) {
+    if (n < 0 || (n > 0 && (!stacks || !views || !images)))
+        return fail(DART_E_INVAL, "bad batch arguments");
+    if (n == 0) return DART_OK;
+    for (int32_t i = 0; i < n; i++)
+        if (!stacks[i]) return fail(DART_E_INVAL, "stacks[%d] is NULL", i);
+    bool force_plain = false;
+    for (int32_t i = 0; i < n; i++)
+        if (views[i].flags & DART_KERNEL_PLAIN) force_plain = true;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (force_plain) {
+        for (int32_t i = 0; i < n; i++) {
+            dart_view v = views[i];
+            v.flags &= ~DART_KERNEL_PLAIN;
+            dart_status st = dart_render(stacks[i], &v, images[i], flux_out ? flux_out + i : nullptr,
+                                         steps_out ? steps_out + i : nullptr, hip_stream);
+            if (st != DART_OK) return st;
+        }
+        return DART_OK;
+    }
+    const dart_tuning tun = tuning_for(stacks[0]);
+    Workspace *ws = get_workspace(stream);
+    std::lock_guard<std::mutex> g(ws->mu);
+
+    // replay key: everything the plan depends on
+    std::vector<uint8_t> key;
+    auto put = [&key](const void *p, size_t b) {
+        const uint8_t *c = (const uint8_t *)p;
+        key.insert(key.end(), c, c + b);
+    };
+    put(&n, sizeof(n));
+    put(&tun, sizeof(tun));
+    for (int32_t i = 0; i < n; i++) {
+        put(&stacks[i], sizeof(void *));
+        put(&stacks[i]->generation, sizeof(stacks[i]->generation));
+        put(&views[i], sizeof(dart_view));
+        put(&images[i], sizeof(void *));
+    }
+
+    // host images render into workspace staging
+    std::vector<void *> dev_images(images, images + n);
+    std::vector<size_t> img_off(n, 0);
+    size_t img_bytes = 0;
+    for (int32_t i = 0; i < n; i++) {
+        if (!(views[i].flags & DART_DEVICE_PTRS)) {
+            img_off[i] = img_bytes;
+            const size_t b = (size_t)views[i].width * views[i].height *
+                             (views[i].out_dtype == DART_F64 ? 8 : 4);
+            img_bytes += (b + 255) & ~(size_t)255;
+        }
+    }
+    const bool replay = ws->graph_exec && key == ws->graph_key && stream != nullptr;
+    if (!replay) {
+        std::vector<Group> groups;
+        // the plan needs image pointers; host ones are patched after reserve
+        std::vector<void *> tmp_images(n);
+        for (int32_t i = 0; i < n; i++)
+            tmp_images[i] = images[i];
+        dart_status st = plan_batch(stacks, views, n, tmp_images.data(), tun, groups);
+        if (st != DART_OK) return st;
+        size_t nv = 0, nt = 0;
+        assign_offsets(groups, &nv, &nt);
+        HIP_TRY(ws_reserve(ws, std::max(nv, (size_t)n), nt, img_bytes / 8 + 1, groups.size() * 4),
+                "workspace");
+        for (Group &gr : groups)
+            for (RayView &rv : gr.views)
+                if (!(views[rv.acc_index].flags & DART_DEVICE_PTRS))
+                    rv.image = (char *)ws->img + img_off[rv.acc_index];
+        // stage descriptors and upload
+        char *h = (char *)ws->stage;
+        pack_descriptors(groups, nv, h);
+        char *ht = h + nv * sizeof(RayView);
+        HIP_TRY(hipMemcpyAsync(ws->views, h, nv * sizeof(RayView), hipMemcpyHostToDevice, stream),
+                "H2D views");
+        HIP_TRY(hipMemcpyAsync(ws->tiles, ht, nt * sizeof(Tile), hipMemcpyHostToDevice, stream),
+                "H2D tiles");
+        HIP_TRY(hipEventRecord(ws->stage_done, stream), "event");
+        drop_graph(ws);
+        if (stream != nullptr) {
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
+            hipError_t e = enqueue_plan(groups, n, ws->acc, ws->views, ws->tiles, tun, ws->device, stream);
+            hipError_t e2 = hipStreamEndCapture(stream, &graph);
+            if (e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return hip_fail(e, "capture batch");
+            }
+            if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "instantiate graph");
+            ws->graph_exec = exec;
+            ws->graph_key = key;
+        } else {
+            HIP_TRY(enqueue_plan(groups, n, ws->acc, ws->views, ws->tiles, tun, ws->device, stream),
+                    "batch kernels");
+        }
+    }
+    if (ws->graph_exec && stream != nullptr) HIP_TRY(hipGraphLaunch(ws->graph_exec, stream), "graph launch");
+    for (int32_t i = 0; i < n; i++) note_use(stacks[i], stream);
+    bool any_host = false;
+    for (int32_t i = 0; i < n; i++) {
+        if (!(views[i].flags & DART_DEVICE_PTRS)) {
+            any_host = true;
+            const size_t b = (size_t)views[i].width * views[i].height *
+                             (views[i].out_dtype == DART_F64 ? 8 : 4);
+            HIP_TRY(hipMemcpyAsync(images[i], (char *)ws->img + img_off[i], b,
+                                   hipMemcpyDeviceToHost, stream),
+                    "D2H image");
+        }
+    }
+    if (flux_out || steps_out || any_host) {
+        std::vector<unsigned long long> acc(2 * (size_t)n);
+        HIP_TRY(hipMemcpyAsync(acc.data(), ws->acc, acc.size() * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, stream),
+                "D2H acc");
+        HIP_TRY(hipStreamSynchronize(stream), "sync");
+        for (int32_t i = 0; i < n; i++) {
+            if (flux_out) memcpy(&flux_out[i], &acc[i], sizeof(double));
+            if (steps_out) steps_out[i] = acc[n + i];
+        }
+    }
+    return DART_OK;
+}
+
+// ------------------------------------------------------------------ autotune
+
+extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view *views, int32_t n,
+                                     int32_t rebrick, dart_tuning *best_out, double *best_ms_out,
+                                     void *hip_stream) {
+    if (n < 1 || !stacks || !views) return fail(DART_E_INVAL, "bad autotune arguments");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    // scratch device images
+    std::vector<dart_view> vv(views, views + n);
+    size_t total = 0;
+    std::vector<size_t> off(n);
+    for (int32_t i = 0; i < n; i++) {
+        vv[i].flags |= DART_DEVICE_PTRS;
+        vv[i].flags &= ~DART_KERNEL_PLAIN;
+        off[i] = total;
+        total += ((size_t)views[i].width * views[i].height * (views[i].out_dtype == DART_F64 ? 8 : 4) + 255) & ~(size_t)255;
+    }
+    void *buf = nullptr;
+    HIP_TRY(hipMalloc(&buf, total), "hipMalloc(autotune images)");
+    std::vector<void *> imgs(n);
+    for (int32_t i = 0; i < n; i++) imgs[i] = (char *)buf + off[i];
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const dart_tuning saved = tuning_for(nullptr);
+    std::vector<dart_tuning> cands;
+    const int shapes[][2] = {{8, 8}, {16, 4}, {4, 16}};
+    const int waves[] = {8, 16, 24, 32};
+    for (auto &sh : shapes)
+        for (int w : waves)
+            for (int order = 0; order < 2; order++) cands.push_back({sh[0], sh[1], w, order});
+    std::vector<std::array<int, 3>> bricks;
+    if (rebrick) bricks = {{4, 4, 4}, {8, 8, 8}, {2, 2, 2}, {8, 8, 2}, {16, 16, 1}};
+    else bricks = {{0, 0, 0}};
+    double best_ms = INFINITY;
+    dart_tuning best = saved;
+    std::array<int, 3> best_brick = {0, 0, 0};
+    dart_status result = DART_OK;
+    for (auto &br : bricks) {
+        if (br[0]) {
+            for (int32_t i = 0; i < n; i++) {
+                bool seen = false;
+                for (int32_t k = 0; k < i; k++) seen |= stacks[k] == stacks[i];
+                if (seen) continue;
+                result = dart_stack_rebrick(stacks[i], br.data(), hip_stream);
+                if (result != DART_OK) break;
+            }
+            if (result != DART_OK) break;
+        }
+        for (const dart_tuning &c : cands) {
+            for (int32_t i = 0; i < n; i++) {
+                stacks[i]->tuning = c;
+                stacks[i]->tuned = true;
+            }
+            // one warm-up (plans and captures), then timed replays
+            result = dart_render_batch(stacks, vv.data(), n, imgs.data(), nullptr, nullptr, hip_stream);
+            if (result != DART_OK) break;
+            float ms_min = INFINITY;
+            for (int rep = 0; rep < 3; rep++) {
+                (void)hipEventRecord(e0, stream);
+                result = dart_render_batch(stacks, vv.data(), n, imgs.data(), nullptr, nullptr, hip_stream);
+                (void)hipEventRecord(e1, stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                ms_min = std::min(ms_min, ms);
+            }
+            if (result != DART_OK) break;
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                best = c;
+                best_brick = br;
+            }
+        }
+        if (result != DART_OK) break;
+    }
+    if (result == DART_OK && best_brick[0] && rebrick) {
+        for (int32_t i = 0; i < n; i++) {
+            bool seen = false;
+            for (int32_t k = 0; k < i; k++) seen |= stacks[k] == stacks[i];
+            if (!seen) result = dart_stack_rebrick(stacks[i], best_brick.data(), hip_stream);
+            if (result != DART_OK) break;
+        }
+    }
+    for (int32_t i = 0; i < n; i++) {
+        stacks[i]->tuning = best;
+        stacks[i]->tuned = result == DART_OK;
+    }
+    (void)hipStreamSynchronize(stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    if (result != DART_OK) return result;
+    if (best_out) *best_out = best;
+    if (best_ms_out) *best_ms_out = best_ms;
+    return DART_OK;
+}
+
+// ------------------------------------------------------------------ counting / probe
+
+extern "C" dart_status dart_count_samples(const dart_stack *s, const dart_view *v,
+                                          uint64_t *samples_out, void *hip_stream) {
+    if (!samples_out) return fail(DART_E_INVAL, "samples_out is NULL");
+    RayView rv;
+    dart_status st = resolve_view(s, v, &rv);
+    if (st != DART_OK) return st;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const uint64_t bits = (uint64_t)s->dev.n[0] * s->dev.n[1] * s->dev.n[2] * s->dev.n_epochs;
+    const uint64_t words = (bits + 31) / 32;
+    const uint64_t u64s = (words + 1) / 2 + 1;
+    unsigned long long *bm = nullptr;
+    HIP_TRY(hipMalloc(&bm, u64s * 8), "hipMalloc(bitmap)");
+    unsigned long long *cnt = bm + (u64s - 1);
+    hipError_t e = launch_fill_u64(bm, u64s, 0ull, stream);
+    if (e == hipSuccess) e = launch_mark(rv, (uint32_t *)bm, stream);
+    if (e == hipSuccess) e = launch_popcount((const uint32_t *)bm, words, cnt, stream);
+    unsigned long long c = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&c, cnt, sizeof(c), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(bm);
+    if (e != hipSuccess) return hip_fail(e, "count samples");
+    *samples_out = c;
+    return DART_OK;
+}
+
+extern "C" dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t bytes,
+                                            int32_t reps, void *hip_stream) {
+    if (!dst || !src || bytes == 0 || bytes % 16 || reps < 1)
+        return fail(DART_E_INVAL, "bad probe arguments");
+    for (int32_t r = 0; r < reps; r++)
+        HIP_TRY(launch_copy(dst, src, bytes, (hipStream_t)hip_stream), "copy kernel");
+    return DART_OK;
+}
