@@ -139,10 +139,22 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
     stacks = [st] * len(views)
     n_img = len(views)
 
-    if args.autotune:
+    tuning = None
+    if args.tuning:
+        tw, th_, w, order, orient, bx, by, bz = [int(x) for x in args.tuning.split(",")]
+        dart.dart_stack_rebrick(st, (bx, by, bz), stream)
+        dart.dart_set_tuning(tw, th_, w, order, orient)
+        tuning = {"tile": [tw, th_], "waves_per_cu": w, "order": order, "orient": orient,
+                  "brick": [bx, by, bz], "fixed": True}
+        log(f"fixed tuning: {tuning}")
+    elif args.autotune:
+        t0 = time.time()
         best, ms = dart.dart_autotune(stacks, views, rebrick=args.rebrick, stream=stream)
-        log(f"autotune: tile {best.tile_w}x{best.tile_h} waves/CU {best.waves_per_cu} "
-            f"order {best.order}: {ms:.3f} ms")
+        info = dart.dart_stack_get_info(st)
+        tuning = {"tile": [best.tile_w, best.tile_h], "waves_per_cu": best.waves_per_cu,
+                  "order": best.order, "orient": best.orient, "brick": list(info.brick),
+                  "best_ms": ms, "tune_s": time.time() - t0}
+        log(f"autotune ({time.time() - t0:.1f} s): {tuning}")
 
     # untimed: cell-steps and flux of every image, compulsory samples
     with torch.cuda.stream(stream):
@@ -204,7 +216,9 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
                "images_per_s_equiv": (n1 / s1) / (cell_steps / n_img)}
         log(f"cpu oracle: {n1 / s1:.3e} cell-steps/s on {threads} threads")
 
-    bw = bandwidth_probe(dart, torch, stream) if not args.profile else None
+    # in profile mode a 1 GiB copy (2 launches) runs as the counter calibration kernel
+    bw = bandwidth_probe(dart, torch, stream, nbytes=(1 << 30) if args.profile else (4 << 30),
+                         reps=2 if args.profile else 10)
     achieved = compulsory / (kernel_ms * 1e-3) / 1e9 if compulsory else None
     roof = None
     if achieved is not None:
@@ -235,6 +249,8 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
         line["speedup_images_per_s_vs_plain"] = line["images_per_s"] / res["plain"]["images_per_s"]
     if "accuracy" in res:
         line["accuracy"] = res["accuracy"]
+    if tuning:
+        line["tuning"] = tuning
     return line
 
 
@@ -259,8 +275,12 @@ def main():
     ap.add_argument("--check", action="store_true", default=True)
     ap.add_argument("--no-check", dest="check", action="store_false")
     ap.add_argument("--check-rays", type=int, default=2048)
-    ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--rebrick", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false", default=True,
+                    help="skip the (untimed) tile / occupancy / brick-shape tuning")
+    ap.add_argument("--no-rebrick", dest="rebrick", action="store_false", default=True)
+    ap.add_argument("--tuning", default=None,
+                    help="fixed launch shape instead of autotuning: "
+                         "tile_w,tile_h,waves_per_cu,order,orient,brick_x,brick_y,brick_z")
     ap.add_argument("--profile", action="store_true",
                     help="timed batched loop only (for rocprofv3 runs)")
     args = ap.parse_args()

@@ -69,7 +69,9 @@ typedef enum { DART_F64 = 0, DART_F32 = 1, DART_F16 = 2, DART_BF16 = 3 } dart_dt
 #define DART_NO_BEAMING 0x2u    /* routine A: D = 1 */
 #define DART_NEAREST_EPOCH 0x4u /* weight 1 on the epoch closest to tbar (ties: earlier) */
 #define DART_NO_KAHAN 0x8u      /* plain (uncompensated) FP32 accumulation */
-#define DART_FORCE_F64_DDA 0x10u /* FP64 ray parameters and FP64 D^p even for 16/32-bit stacks */
+#define DART_FORCE_F64_DDA 0x10u /* FP64 ray parameters (DDA crossings, retarded times) even
+                                    for 16/32-bit stacks; chosen by itself when a ray may
+                                    cross more than 4096 cells */
 #define DART_DEVICE_PTRS 0x20u  /* load: field pointers are device pointers;
                                    view: the image pointer is a device pointer */
 #define DART_KERNEL_PLAIN 0x40u /* dart_render_batch: force the one-launch-per-image kernel */
@@ -87,10 +89,10 @@ typedef struct dart_server dart_server;
  *   storage      resident element type; DART_F16 / DART_BF16 round to nearest even
  *   emissivity   [M][nz][ny][nx], C order (x fastest)
  *   velocity     [M][nz][ny][nx][3] (beta_x, beta_y, beta_z)
- *   flags        DART_DEVICE_PTRS: arrays are device memory; the copy is
- *                stream-ordered and the caller keeps them alive until the
- *                stream passes this call.  Host arrays: the call returns after
- *                the copy has finished.
+ *   flags        DART_DEVICE_PTRS: arrays are device memory, converted in
+ *                place on hip_stream.  Either way the call returns after the
+ *                conversion and its validation have finished, so the caller may
+ *                release the arrays on return.
  *   hip_stream   hipStream_t or NULL (default stream)
  * Every value must be finite and |beta| < 1 before and after rounding to the
  * storage type, else DART_E_RANGE names the first bad element.
@@ -174,7 +176,11 @@ dart_status dart_render_batch(const dart_stack *const *stacks, const dart_view *
 typedef struct {
     int32_t tile_w, tile_h;  /* pixels per wavefront tile, tile_w * tile_h == 64 */
     int32_t waves_per_cu;    /* resident waves per compute unit for the persistent grid */
-    int32_t order;           /* 0: tiles in spatial order, 1: longest estimated tile first */
+    int32_t order;           /* tile queue order: 0 row-major, 1 longest estimated tile
+                                first, 2 Z-order (Morton) */
+    int32_t orient;          /* 1: per view, turn the tile so that its long side follows
+                                the image-plane projection of the bricks' long axis
+                                (lanes of a wavefront then share cache lines) */
 } dart_tuning;
 
 /* Times the batched kernel on the given views over candidate tile shapes,

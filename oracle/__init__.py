@@ -89,6 +89,9 @@ def _load():
                                      ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
         lib.orc_count_samples.restype = ctypes.c_longlong
         lib.orc_count_samples.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View)]
+        lib.orc_count_blocks.restype = ctypes.c_longlong
+        lib.orc_count_blocks.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View), ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int]
         lib.orc_camera_basis.restype = None
         lib.orc_camera_basis.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View),
                                          ctypes.c_void_p]
@@ -216,6 +219,22 @@ def count_samples(stack: Stack, view: View) -> int:
     """Distinct (cell, epoch) samples with positive weight over the image."""
     lib = _load()
     return int(lib.orc_count_samples(ctypes.byref(stack._cgrid()), ctypes.byref(view._cview())))
+
+
+def count_blocks(dims, times, view: View, block=(1, 1, 1)) -> int:
+    """Distinct (block, epoch) pairs with positive weight over the image, for
+    blocks of block[0] x block[1] x block[2] unit cells (geometry only)."""
+    lib = _load()
+    g = _Grid()
+    g.n[:] = [int(d) for d in dims]
+    g.cell[:] = [1.0, 1.0, 1.0]
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    g.n_epochs = len(t)
+    g.times = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    g.dtype = 0
+    g.j = None
+    g.beta = None
+    return int(lib.orc_count_blocks(ctypes.byref(g), ctypes.byref(view._cview()), *block))
 
 
 def camera_basis(stack: Stack, view: View):

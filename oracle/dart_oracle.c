@@ -383,10 +383,12 @@ int orc_segments(const orc_grid *g, const orc_view *v, int i, int j, double *out
     return nseg;
 }
 
-/* Number of distinct (cell, epoch) samples that receive a positive weight on
- * any ray of the image: the compulsory samples an image must read. */
-long long orc_count_samples(const orc_grid *g, const orc_view *v) {
-    size_t ncell = (size_t)g->n[0] * g->n[1] * g->n[2];
+/* Number of distinct (block, epoch) pairs that receive a positive weight on
+ * any ray of the image, for blocks of bx x by x bz cells (1 x 1 x 1: the
+ * compulsory samples an image must read).  Reads no field values. */
+long long orc_count_blocks(const orc_grid *g, const orc_view *v, int bx, int by, int bz) {
+    int nbx = (g->n[0] + bx - 1) / bx, nby = (g->n[1] + by - 1) / by, nbz = (g->n[2] + bz - 1) / bz;
+    size_t ncell = (size_t)nbx * nby * nbz;
     size_t nbits = ncell * (size_t)g->n_epochs;
     uint8_t *seen = (uint8_t *)calloc(nbits, 1);
     if (!seen) return -1;
@@ -404,7 +406,10 @@ long long orc_count_samples(const orc_grid *g, const orc_view *v) {
                 int k = orc_epoch_weights(g->times, g->n_epochs, tbar, v->flags, ms, ws);
                 for (int r = 0; r < k; r++) {
                     if (!(ws[r] > 0.0)) continue;
-                    size_t bit = (size_t)ms[r] * ncell + (size_t)seg[3 * q + 2];
+                    size_t c = (size_t)seg[3 * q + 2];
+                    size_t x = c % g->n[0], y = (c / g->n[0]) % g->n[1], z = c / ((size_t)g->n[0] * g->n[1]);
+                    size_t blk = ((z / bz) * nby + y / by) * nbx + x / bx;
+                    size_t bit = (size_t)ms[r] * ncell + blk;
                     if (!seen[bit]) { seen[bit] = 1; count++; }
                 }
             }
@@ -412,4 +417,8 @@ long long orc_count_samples(const orc_grid *g, const orc_view *v) {
     free(seg);
     free(seen);
     return count;
+}
+
+long long orc_count_samples(const orc_grid *g, const orc_view *v) {
+    return orc_count_blocks(g, v, 1, 1, 1);
 }

@@ -16,22 +16,23 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build() -> str:
-    obj_dir = os.path.join(HERE, "_build")
+def build(out: str = OUT, defines=()) -> str:
+    obj_dir = os.path.join(HERE, "_build" + ("_" + "_".join(d.replace("=", "") for d in defines) if defines else ""))
     os.makedirs(obj_dir, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
-        subprocess.check_call([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
+        subprocess.check_call([HIPCC] + FLAGS + ["-D" + d for d in defines]
+                              + ["-c", os.path.join(CSRC, src), "-o", obj])
         return obj
 
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
                           + ["-lpthread"])
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -22,6 +22,7 @@ enum : uint32_t {
 struct StackDev {
     const void *data;       // resident records
     const double *times;    // [M] epoch times (device)
+    const double *inv_dt;   // [M] 1 / (t_{m+1} - t_m), 0 for the last epoch (device)
     uint64_t epoch_stride;  // records per epoch (padded to whole bricks)
     int32_t n[3];           // cells per axis
     int32_t nb[3];          // bricks per axis
@@ -34,6 +35,7 @@ struct StackDev {
 // One view, resolved on the host in FP64.
 struct RayView {
     double shat[3], eu[3], ev[3], centre[3];
+    double inv_shat[3];     // 1 / s_hat per axis (0 where s_hat has a zero component)
     double ps;              // pixel scale
     double t_obs;
     double s_lo, s_hi;      // temporal window expressed in s: [t_obs - t_{M-1}, t_obs - t_0]
@@ -45,6 +47,7 @@ struct RayView {
     void *image;            // [height][width] float or double (device)
     int32_t out_f64;
     int32_t acc_index;      // slot in the flux / step accumulators
+    int32_t tile_w_log2;    // batched kernel: tile width 1 << tile_w_log2, height 64 >> it
     StackDev st;
 };
 
@@ -60,7 +63,6 @@ struct BatchLaunch {
     uint32_t n_tiles;
     uint32_t *head;         // tile queue heads, one per XCD queue
     uint32_t n_queues;
-    uint32_t tile_w_log2;   // tile width = 1 << tile_w_log2, tile height = 64 >> tile_w_log2
     double *flux_acc;
     unsigned long long *step_acc;
 };

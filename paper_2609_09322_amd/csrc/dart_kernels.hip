@@ -38,22 +38,23 @@ __device__ __forceinline__ uint32_t cell_offset(const StackDev &st, int x, int y
     return (brick << (st.lb[0] + st.lb[1] + st.lb[2])) | inner;
 }
 
-template <int S> struct RecT;
-template <> struct RecT<ST_F64> { using raw = double4; using val = double; };
-template <> struct RecT<ST_F32> { using raw = float4; using val = float; };
-template <> struct RecT<ST_F16> { using raw = uint2; using val = float; };
-template <> struct RecT<ST_BF16> { using raw = uint2; using val = float; };
+// Raw records as clang vector types: (j, beta_x, beta_y, beta_z) in the
+// storage type; 16-bit records are two 32-bit words (j | bx << 16, by | bz << 16).
+typedef double rec_f64 __attribute__((ext_vector_type(4)));
+typedef float rec_f32 __attribute__((ext_vector_type(4)));
+typedef unsigned int rec_h16 __attribute__((ext_vector_type(2)));
 
+template <int S> struct RecT;
+template <> struct RecT<ST_F64> { using raw = rec_f64; using val = double; };
+template <> struct RecT<ST_F32> { using raw = rec_f32; using val = float; };
+template <> struct RecT<ST_F16> { using raw = rec_h16; using val = float; };
+template <> struct RecT<ST_BF16> { using raw = rec_h16; using val = float; };
+
+// Records are read through global-address-space pointers (plain global loads).
 template <int S>
-__device__ __forceinline__ typename RecT<S>::raw load_rec(const StackDev &st, uint64_t rec) {
-    const typename RecT<S>::raw *p = (const typename RecT<S>::raw *)st.data;
-    if constexpr (S == ST_F64) {
-        const double2 *q = (const double2 *)st.data;
-        double2 a = q[2 * rec], b = q[2 * rec + 1];
-        return double4{a.x, a.y, b.x, b.y};
-    } else {
-        return p[rec];
-    }
+__device__ __forceinline__ typename RecT<S>::raw load_grec(
+    const typename RecT<S>::raw __attribute__((address_space(1))) *p) {
+    return *p;
 }
 
 __device__ __forceinline__ float h2f(uint32_t bits16) {
@@ -105,22 +106,31 @@ __device__ __forceinline__ typename RecT<S>::val boosted(const typename RecT<S>:
 
 // ------------------------------------------------------------------ one ray
 
-// Marches pixel (pi, pj) of view v.  Returns the intensity (FP64 for the
-// caller's reductions) and adds the counted cell-steps to nsteps.  With MARK
-// the (epoch, cell) samples of positive weight are set in `bitmap`
-// ([M][nz][ny][nx] bits) and nothing is summed.
-template <int S, typename R, bool MARK>
-__device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32_t *bitmap,
-                                        uint32_t &nsteps) {
-    using A = typename std::conditional<S == ST_F64, double, float>::type;
+// DDA state of one ray.  Per axis the plane crossings ahead of the ray form the
+// sequence base + c * ds_axis (c = crossings made so far along that axis): the
+// cell's chord is [max of the planes behind, min of the planes ahead].
+template <typename R>
+struct Ray {
+    int x, y, z;
+    int sx, sy, sz;      // step per axis (-1, 0, +1)
+    int c0, c1, c2;      // crossings made per axis
+    R b0, b1, b2;        // s of the first plane ahead per axis
+    R d0, d1, d2;        // plane spacing per axis (Eq. 11)
+    R sa0, sa1, sa2;     // s of the plane ahead
+    R sb0, sb1, sb2;     // s of the plane behind
+    R stop;              // min(exit of the grid, end of the temporal window)
+};
+
+// FP64 set-up of pixel (pi, pj): slab test, clip to the window, starting cell
+// and crossing sequences.  False when no cell of the ray can contribute.
+template <typename R>
+__device__ __forceinline__ bool ray_setup(const RayView &v, int pi, int pj, Ray<R> &r) {
     const StackDev &st = v.st;
     const double u = (pi + 0.5 - 0.5 * v.width) * v.ps;
     const double w = (pj + 0.5 - 0.5 * v.height) * v.ps;
     double o[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) o[a] = v.centre[a] + u * v.eu[a] + w * v.ev[a];
-
-    // slab test against [0, n dx) per axis
     double s_in = -INFINITY, s_out = INFINITY;
     bool hit = true;
 #pragma unroll
@@ -130,19 +140,17 @@ __device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32
         if (d == 0.0) {
             if (o[a] < 0.0 || o[a] >= hi) hit = false;
         } else {
-            double t0 = (0.0 - o[a]) / d, t1 = (hi - o[a]) / d;
+            const double t0 = (0.0 - o[a]) * v.inv_shat[a], t1 = (hi - o[a]) * v.inv_shat[a];
             s_in = fmax(s_in, fmin(t0, t1));
             s_out = fmin(s_out, fmax(t0, t1));
         }
     }
     const double s_start = fmax(s_in, v.s_lo);
     const double s_stop = fmin(s_out, v.s_hi);
-    if (!hit || !(s_start < s_stop) || !(s_in < s_out)) return 0.0;
-    if ((v.flags & F_NO_LOOKBACK) && v.fixed_m < 0) return 0.0;
-
-    // starting cell and per-axis crossing sequences
+    if (!hit || !(s_start < s_stop) || !(s_in < s_out)) return false;
+    if ((v.flags & F_NO_LOOKBACK) && v.fixed_m < 0) return false;
     int idx[3], stp[3];
-    R base[3], dsa[3];
+    R base[3], sp[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const double d = v.shat[a];
@@ -153,120 +161,235 @@ __device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32
         if (d == 0.0) {
             stp[a] = 0;
             base[a] = (R)INFINITY;
-            dsa[a] = (R)0;
+            sp[a] = (R)0;
         } else {
             stp[a] = d > 0.0 ? 1 : -1;
             const double plane = (d > 0.0 ? (k + 1) : k) * st.cell[a];
-            base[a] = (R)((plane - o[a]) / d);
-            dsa[a] = (R)(st.cell[a] / fabs(d));
+            base[a] = (R)((plane - o[a]) * v.inv_shat[a]);
+            sp[a] = (R)(st.cell[a] * fabs(v.inv_shat[a]));
         }
     }
-    // crossing counters: ahead plane = base + c ds, behind plane = base + (c - 1) ds
-    int c0 = 0, c1 = 0, c2 = 0;
-    R sa0 = base[0], sa1 = base[1], sa2 = base[2];
-    R sb0 = stp[0] ? base[0] - dsa[0] : (R)-INFINITY;
-    R sb1 = stp[1] ? base[1] - dsa[1] : (R)-INFINITY;
-    R sb2 = stp[2] ? base[2] - dsa[2] : (R)-INFINITY;
-    int x = idx[0], y = idx[1], z = idx[2];
+    r.x = idx[0]; r.y = idx[1]; r.z = idx[2];
+    r.sx = stp[0]; r.sy = stp[1]; r.sz = stp[2];
+    r.c0 = r.c1 = r.c2 = 0;
+    r.b0 = base[0]; r.b1 = base[1]; r.b2 = base[2];
+    r.d0 = sp[0]; r.d1 = sp[1]; r.d2 = sp[2];
+    r.sa0 = base[0]; r.sa1 = base[1]; r.sa2 = base[2];
+    r.sb0 = stp[0] ? base[0] - sp[0] : (R)-INFINITY;
+    r.sb1 = stp[1] ? base[1] - sp[1] : (R)-INFINITY;
+    r.sb2 = stp[2] ? base[2] - sp[2] : (R)-INFINITY;
+    r.stop = (R)s_stop;
+    return true;
+}
 
-    const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi, r_stop = (R)s_stop;
+// Step to the neighbour across the nearest face; false when leaving the grid.
+template <typename R>
+__device__ __forceinline__ bool ray_advance(const StackDev &st, Ray<R> &r) {
+    if (r.sa0 <= r.sa1 && r.sa0 <= r.sa2) {
+        r.x += r.sx;
+        if ((unsigned)r.x >= (unsigned)st.n[0]) return false;
+        r.c0++;
+        r.sb0 = r.sa0;
+        r.sa0 = fma((R)r.c0, r.d0, r.b0);
+    } else if (r.sa1 <= r.sa2) {
+        r.y += r.sy;
+        if ((unsigned)r.y >= (unsigned)st.n[1]) return false;
+        r.c1++;
+        r.sb1 = r.sa1;
+        r.sa1 = fma((R)r.c1, r.d1, r.b1);
+    } else {
+        r.z += r.sz;
+        if ((unsigned)r.z >= (unsigned)st.n[2]) return false;
+        r.c2++;
+        r.sb2 = r.sa2;
+        r.sa2 = fma((R)r.c2, r.d2, r.b2);
+    }
+    return true;
+}
+
+// Epoch bracket in s: a_m = t_obs - t_m decreases with m; the bracket m holds
+// a_{m+1} <= s_mid <= a_m.  s_mid only grows along a ray, so m only moves down.
+template <typename R>
+struct Bracket {
+    int m;
+    R am, am1, inv_dt;
+};
+
+typedef const double __attribute__((address_space(1))) gdouble;
+
+template <typename R>
+__device__ __forceinline__ void bracket_init(const RayView &v, bool lookback, Bracket<R> &b) {
+    const StackDev &st = v.st;
+    gdouble *t = (gdouble *)st.times, *idt = (gdouble *)st.inv_dt;
+    const int M = st.n_epochs;
+    b.m = lookback ? (M >= 2 ? M - 2 : 0) : v.fixed_m;
+    b.am = (R)(v.t_obs - t[b.m]);
+    b.am1 = M >= 2 ? (R)(v.t_obs - t[b.m + 1]) : b.am;
+    b.inv_dt = M >= 2 ? (R)idt[b.m] : (R)0;
+}
+
+template <typename R>
+__device__ __forceinline__ void bracket_seek(const RayView &v, R mid, Bracket<R> &b) {
+    gdouble *t = (gdouble *)v.st.times, *idt = (gdouble *)v.st.inv_dt;
+    while (b.m > 0 && mid > b.am) {
+        b.m--;
+        b.am1 = b.am;
+        b.am = (R)(v.t_obs - t[b.m]);
+        b.inv_dt = (R)idt[b.m];
+    }
+}
+
+// Sample marking for the compulsory-bytes count: sets the (epoch, cell) bits
+// of positive weight in `bitmap` ([M][nz][ny][nx] bits).
+template <typename R>
+__device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint32_t *bitmap) {
+    Ray<R> r;
+    if (!ray_setup(v, pi, pj, r)) return;
+    const StackDev &st = v.st;
+    const bool lookback = !(v.flags & F_NO_LOOKBACK);
+    const bool single = (v.flags & F_NEAREST) || st.n_epochs == 1;
+    const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
+    Bracket<R> br;
+    bracket_init(v, lookback, br);
+    const uint64_t ncell = (uint64_t)st.n[0] * st.n[1] * st.n[2];
+    for (int guard = st.n[0] + st.n[1] + st.n[2] + 3; guard > 0; guard--) {
+        const R entry = fmax(r.sb0, fmax(r.sb1, r.sb2));
+        const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
+        if (entry >= r.stop) break;
+        const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
+        if (ds > (R)0 && mid >= r_lo && mid <= r_hi) {
+            R wt = (R)v.fixed_w;
+            if (lookback) {
+                bracket_seek(v, mid, br);
+                wt = (br.am - mid) * br.inv_dt;
+            }
+            int m0 = br.m;
+            if (single && st.n_epochs >= 2) {
+                const bool later = lookback ? (mid - br.am1) < (br.am - mid) : wt > (R)0.5;
+                m0 = later ? br.m + 1 : br.m;
+            }
+            const uint64_t lin = ((uint64_t)r.z * st.n[1] + r.y) * st.n[0] + r.x;
+            if (single || wt < (R)1) {
+                const uint64_t b = (uint64_t)m0 * ncell + lin;
+                atomicOr(&bitmap[b >> 5], 1u << (b & 31));
+            }
+            if (!single && wt > (R)0) {
+                const uint64_t b = (uint64_t)(m0 + 1) * ncell + lin;
+                atomicOr(&bitmap[b >> 5], 1u << (b & 31));
+            }
+        }
+        if (!ray_advance(st, r)) break;
+    }
+}
+
+// Cells walked per batch: a lane walks CELLS_PER_BATCH cells of its ray, then
+// issues all their record loads back to back, then consumes them.
+#ifndef DART_CELLS_PER_BATCH
+#define DART_CELLS_PER_BATCH 4
+#endif
+constexpr int CELLS_PER_BATCH = DART_CELLS_PER_BATCH;
+
+// Marches pixel (pi, pj) of view v and returns its intensity (FP64 for the
+// caller's reductions); adds the counted cell-steps to nsteps.
+//
+// The walk does not depend on the data it reads, so each lane first walks a
+// batch of cells (chord, epoch weight, record addresses), then requests the
+// 2 x CELLS_PER_BATCH records at once and consumes them after a single wait:
+// many gathers per lane in flight instead of one dependent load per step.
+template <int S, typename R>
+__device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32_t &nsteps) {
+    using A = typename std::conditional<S == ST_F64, double, float>::type;
+    using Raw = typename RecT<S>::raw;
+    using GRaw = const Raw __attribute__((address_space(1)));
+    constexpr int K = CELLS_PER_BATCH;
+    Ray<R> r;
+    if (!ray_setup(v, pi, pj, r)) return 0.0;
+    const StackDev &st = v.st;
     const bool lookback = !(v.flags & F_NO_LOOKBACK);
     const bool beaming = !(v.flags & F_NO_BEAMING);
-    const bool single = (v.flags & F_NEAREST) || st.n_epochs == 1;
-    const bool kahan = !(v.flags & F_NO_KAHAN);
     const int M = st.n_epochs;
-
-    // epoch bracket in s: a_m = t_obs - t_m decreases with m; interval m holds
-    // a_{m+1} <= s_mid <= a_m.  NO_LOOKBACK uses the bracket at t_obs.
-    int m = lookback ? (M >= 2 ? M - 2 : 0) : v.fixed_m;
-    R am = (R)(v.t_obs - st.times[m]);
-    R am1 = M >= 2 ? (R)(v.t_obs - st.times[m + 1]) : am;
-    R inv_dt = M >= 2 ? (R)(1.0 / (st.times[m + 1] - st.times[m])) : (R)0;
-    const R fixed_w = (R)v.fixed_w;
-
+    const bool single = (v.flags & F_NEAREST) || M == 1;
+    const bool kahan = !(v.flags & F_NO_KAHAN);
+    const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
+    GRaw *gdata = (GRaw *)st.data;
+    const uint64_t estride = st.epoch_stride;
+    // offset of the second record: the next epoch, or the same record when
+    // only one epoch is used
+    const uint64_t second = single ? 0 : estride;
+    Bracket<R> br;
+    bracket_init(v, lookback, br);
+    GRaw *ebase = gdata + (uint64_t)br.m * estride;  // records of epoch br.m
+    int ebase_m = br.m;
     A sum = 0, comp = 0;
     uint32_t count = 0;
-    const uint64_t estride = st.epoch_stride;
-    // a ray visits at most nx + ny + nz cells; the cap makes termination
-    // independent of floating-point corner cases in the face selection
-    for (int guard = st.n[0] + st.n[1] + st.n[2] + 3; guard > 0; guard--) {
-        const R entry = fmax(sb0, fmax(sb1, sb2));
-        const R exit = fmin(sa0, fmin(sa1, sa2));
-        if (entry >= r_stop) break;
-        const R ds = exit - entry;
-        const R mid = (R)0.5 * (entry + exit);
-        if (ds > (R)0 && mid >= r_lo && mid <= r_hi) {
-            R wt;
-            if (lookback) {
-                while (m > 0 && mid > am) {
-                    m--;
-                    am1 = am;
-                    am = (R)(v.t_obs - st.times[m]);
-                    inv_dt = (R)(1.0 / (st.times[m + 1] - st.times[m]));
-                }
-                wt = (am - mid) * inv_dt;
-            } else {
-                wt = fixed_w;
-            }
-            int m0 = m;
-            if (single) {
-                if (M >= 2) {
-                    const bool later = lookback ? (mid - am1) < (am - mid) : wt > (R)0.5;
-                    m0 = later ? m + 1 : m;
-                }
-                wt = (R)0;
-            }
-            const uint32_t off = cell_offset(st, x, y, z);
-            count++;
-            if constexpr (MARK) {
-                const uint64_t ncell = (uint64_t)st.n[0] * st.n[1] * st.n[2];
-                const uint64_t lin = ((uint64_t)z * st.n[1] + y) * st.n[0] + x;
-                if (single || wt < (R)1) {
-                    const uint64_t b = (uint64_t)m0 * ncell + lin;
-                    atomicOr(&bitmap[b >> 5], 1u << (b & 31));
-                }
-                if (!single && wt > (R)0) {
-                    const uint64_t b = (uint64_t)(m0 + 1) * ncell + lin;
-                    atomicOr(&bitmap[b >> 5], 1u << (b & 31));
-                }
-            } else {
-                const auto r0 = load_rec<S>(st, (uint64_t)m0 * estride + off);
-                A val = (A)boosted<S>(r0, v, beaming);
-                if (!single) {
-                    const auto r1 = load_rec<S>(st, (uint64_t)(m0 + 1) * estride + off);
-                    const A b1 = (A)boosted<S>(r1, v, beaming);
-                    val = val + (A)wt * (b1 - val);
-                }
-                const A term = (A)ds * val;
-                if (kahan) {
-                    const A yk = term - comp;
-                    const A tk = sum + yk;
-                    comp = (tk - sum) - yk;
-                    sum = tk;
+    bool alive = true;
+
+    for (int guard = (st.n[0] + st.n[1] + st.n[2]) / K + 3; guard > 0 && alive; guard--) {
+        GRaw *addr[K];
+        R cds[K], cw[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            addr[k] = gdata;  // a valid address for cells past the end of the ray
+            cds[k] = (R)0;
+            cw[k] = (R)0;
+            if (alive) {
+                const R entry = fmax(r.sb0, fmax(r.sb1, r.sb2));
+                const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
+                if (entry >= r.stop) {
+                    alive = false;
                 } else {
-                    sum += term;
+                    const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
+                    const bool contrib = ds > (R)0 && mid >= r_lo && mid <= r_hi;
+                    R wt = (R)v.fixed_w;
+                    if (lookback) {
+                        bracket_seek(v, mid, br);
+                        wt = (br.am - mid) * br.inv_dt;
+                    }
+                    if (br.m != ebase_m) {
+                        ebase = gdata + (uint64_t)br.m * estride;
+                        ebase_m = br.m;
+                    }
+                    GRaw *e0 = ebase;
+                    if (single) {
+                        if (M >= 2) {
+                            const bool later =
+                                lookback ? (mid - br.am1) < (br.am - mid) : wt > (R)0.5;
+                            if (later) e0 = ebase + estride;
+                        }
+                        wt = (R)0;
+                    }
+                    addr[k] = e0 + cell_offset(st, r.x, r.y, r.z);
+                    cds[k] = contrib ? ds : (R)0;
+                    cw[k] = wt;
+                    count += contrib ? 1u : 0u;
+                    alive = ray_advance(st, r);
                 }
             }
         }
-        // advance to the neighbour across the nearest face
-        if (sa0 <= sa1 && sa0 <= sa2) {
-            x += stp[0];
-            if ((unsigned)x >= (unsigned)st.n[0]) break;
-            c0++;
-            sb0 = sa0;
-            sa0 = fma((R)c0, dsa[0], base[0]);
-        } else if (sa1 <= sa2) {
-            y += stp[1];
-            if ((unsigned)y >= (unsigned)st.n[1]) break;
-            c1++;
-            sb1 = sa1;
-            sa1 = fma((R)c1, dsa[1], base[1]);
-        } else {
-            z += stp[2];
-            if ((unsigned)z >= (unsigned)st.n[2]) break;
-            c2++;
-            sb2 = sa2;
-            sa2 = fma((R)c2, dsa[2], base[2]);
+        Raw r0[K], r1[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            r0[k] = load_grec<S>(addr[k]);
+            r1[k] = load_grec<S>(addr[k] + second);
+        }
+        // Every lane consumes all K cells: a cell past the end of the ray or
+        // outside the window has ds = 0 (its records, validated at load, are
+        // finite), and an unconditional use keeps the compiler from sinking
+        // the loads back into a branch.
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            A val = (A)boosted<S>(r0[k], v, beaming);
+            const A b1 = (A)boosted<S>(r1[k], v, beaming);
+            val = val + (A)cw[k] * (b1 - val);
+            const A term = (A)cds[k] * val;
+            if (kahan) {
+                const A yk = term - comp;
+                const A tk = sum + yk;
+                comp = (tk - sum) - yk;
+                sum = tk;
+            } else {
+                sum += term;
+            }
         }
     }
     nsteps += count;
@@ -304,7 +427,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
     uint32_t ns = 0;
     if (idx < npix) {
         const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
-        val = march<S, R, false>(v, pi, pj, nullptr, ns);
+        val = march<S, R>(v, pi, pj, ns);
         store_pixel(v, pi, pj, val);
     }
     const double fs = wave_sum(val);
@@ -325,7 +448,6 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
     const int lane = threadIdx.x & 63;
     const uint32_t nq = bl.n_queues;
     const uint32_t q0 = blockIdx.x % nq;
-    const uint32_t tw_log2 = bl.tile_w_log2;
     for (uint32_t qi = 0; qi < nq;) {
         const uint32_t q = (q0 + qi) % nq;
         const uint32_t begin = (uint32_t)(((uint64_t)bl.n_tiles * q) / nq);
@@ -340,6 +462,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
         const Tile tile = bl.tiles[begin + t];
         const uint32_t vi = __builtin_amdgcn_readfirstlane(tile.view);
         const RayView &v = bl.views[vi];
+        const uint32_t tw_log2 = (uint32_t)__builtin_amdgcn_readfirstlane(v.tile_w_log2);
         const int pi = (int)(__builtin_amdgcn_readfirstlane(tile.tx) << tw_log2) +
                        (lane & ((1 << tw_log2) - 1));
         const int pj = (int)(__builtin_amdgcn_readfirstlane(tile.ty) << (6 - tw_log2)) +
@@ -347,7 +470,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
         double val = 0.0;
         uint32_t ns = 0;
         if (pi < v.width && pj < v.height) {
-            val = march<S, R, false>(v, pi, pj, nullptr, ns);
+            val = march<S, R>(v, pi, pj, ns);
             store_pixel(v, pi, pj, val);
         }
         const double fs = wave_sum(val);
@@ -365,8 +488,7 @@ __global__ void __launch_bounds__(256) k_mark(RayView v, uint32_t *bitmap) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long npix = (long long)v.width * v.height;
     if (idx >= npix) return;
-    uint32_t ns = 0;
-    march<S, R, true>(v, (int)(idx % v.width), (int)(idx / v.width), bitmap, ns);
+    mark_ray<R>(v, (int)(idx % v.width), (int)(idx / v.width), bitmap);
 }
 
 __global__ void __launch_bounds__(256) k_popcount(const uint32_t *bm, uint64_t words,

@@ -19,7 +19,7 @@ struct dart_stack {
     uint64_t bytes = 0;
     uint64_t generation = 0;  // bumped whenever the resident layout or data change
     int device = 0;
-    dart_tuning tuning{8, 8, 16, 0};
+    dart_tuning tuning{32, 2, 8, 0, 1};
     bool tuned = false;
     std::mutex mu;
     std::vector<std::pair<hipStream_t, hipEvent_t>> uses;  // last render per stream
@@ -44,7 +44,6 @@ struct Group {
     std::vector<RayView> views;
     std::vector<Tile> tiles;
     size_t view_off = 0, tile_off = 0;  // offsets in the uploaded descriptor arrays
-    uint32_t tile_w_log2 = 3;
     uint32_t n_queues = 8;
 };
 

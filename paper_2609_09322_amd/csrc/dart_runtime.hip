@@ -101,9 +101,12 @@ static void layout(dart_stack *s, const int lb[3]) {
 }
 
 static void default_brick(int store, int lb[3]) {
-    // 4x4x4 cells: 512 B (16-bit) to 2 KB (FP64) per brick, several 128-B lines
-    (void)store;
-    lb[0] = lb[1] = lb[2] = 2;
+    // Bricks of about one 128-B cache line: 2x2x2 FP32 records (16 B each) or
+    // 4x2x2 16-bit records (8 B); FP64 records (32 B) use 2x2x2 (two lines).
+    // A cube-like line serves neighbouring rays of any orientation.
+    lb[0] = store == ST_F16 || store == ST_BF16 ? 2 : 1;
+    lb[1] = 1;
+    lb[2] = 1;
 }
 
 static dart_status check_geometry(const int32_t dims[3], const double cell[3], int32_t M,
@@ -154,12 +157,18 @@ extern "C" dart_status dart_stack_create(const int32_t dims[3], const double cel
     void *data = nullptr, *t = nullptr;
     hipError_t e = hipMalloc(&data, s->bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(stack)");
-    e = hipMalloc(&t, sizeof(double) * n_epochs);
+    // epoch times followed by 1 / (t_{m+1} - t_m) (0 for the last epoch)
+    std::vector<double> tab(2 * (size_t)n_epochs, 0.0);
+    for (int32_t m = 0; m < n_epochs; m++) {
+        tab[m] = epoch_times[m];
+        if (m + 1 < n_epochs) tab[n_epochs + m] = 1.0 / (epoch_times[m + 1] - epoch_times[m]);
+    }
+    e = hipMalloc(&t, sizeof(double) * tab.size());
     if (e != hipSuccess) {
         (void)hipFree(data);
         return hip_fail(e, "hipMalloc(times)");
     }
-    e = hipMemcpy(t, epoch_times, sizeof(double) * n_epochs, hipMemcpyHostToDevice);
+    e = hipMemcpy(t, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(data);
         (void)hipFree(t);
@@ -167,6 +176,7 @@ extern "C" dart_status dart_stack_create(const int32_t dims[3], const double cel
     }
     s->dev.data = data;
     s->dev.times = (const double *)t;
+    s->dev.inv_dt = (const double *)t + n_epochs;
     *out = s.release();
     return DART_OK;
 }
@@ -389,6 +399,7 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     const double nhat[3] = {st * cp, st * sp, ct};
     for (int a = 0; a < 3; a++) {
         rv->shat[a] = -nhat[a];
+        rv->inv_shat[a] = rv->shat[a] != 0.0 ? 1.0 / rv->shat[a] : 0.0;
         rv->centre[a] = 0.5 * s->dev.n[a] * s->dev.cell[a];
     }
     rv->eu[0] = -sp; rv->eu[1] = cp; rv->eu[2] = 0.0;
@@ -538,7 +549,7 @@ extern "C" dart_status dart_render(const dart_stack *s, const dart_view *v, void
 // ------------------------------------------------------------------ tuning
 
 static std::mutex g_tune_mu;
-static dart_tuning g_tuning = {8, 8, 16, 0};
+static dart_tuning g_tuning = {32, 2, 8, 0, 1};
 
 static dart_status check_tuning(const dart_tuning *t) {
     if (!t) return fail(DART_E_INVAL, "tuning is NULL");
@@ -548,7 +559,8 @@ static dart_status check_tuning(const dart_tuning *t) {
                     t->tile_h);
     if (t->waves_per_cu < 4 || t->waves_per_cu > 64 || t->waves_per_cu % 4)
         return fail(DART_E_INVAL, "waves_per_cu must be a multiple of 4 in [4, 64]");
-    if (t->order != 0 && t->order != 1) return fail(DART_E_INVAL, "order must be 0 or 1");
+    if (t->order < 0 || t->order > 2) return fail(DART_E_INVAL, "order must be 0, 1 or 2");
+    if (t->orient != 0 && t->orient != 1) return fail(DART_E_INVAL, "orient must be 0 or 1");
     return DART_OK;
 }
 
@@ -602,8 +614,7 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
                              void *const *images, const dart_tuning &tun,
                              std::vector<Group> &groups) {
     groups.clear();
-    const int lw = ilog2_exact(tun.tile_w);
-    const int tw = tun.tile_w, th = tun.tile_h;
+    const int lw0 = ilog2_exact(tun.tile_w);
     std::map<int, size_t> gindex;
     for (int32_t i = 0; i < n; i++) {
         RayView rv;
@@ -622,7 +633,22 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         }
         Group &g = groups[it->second];
         const uint32_t vi = (uint32_t)g.views.size();
+        // Orientation of the tile: its long side follows the image-plane
+        // projection of the bricks' long axis, so that the lanes of one wave
+        // read neighbouring cells of the same cache lines.
+        int lw = lw0;
+        if (tun.orient) {
+            int a = 0;
+            for (int k = 1; k < 3; k++)
+                if (rv.st.lb[k] > rv.st.lb[a]) a = k;
+            const bool elongated = rv.st.lb[a] > std::min(rv.st.lb[0], std::min(rv.st.lb[1], rv.st.lb[2]));
+            const bool long_u = tun.tile_w >= tun.tile_h;
+            const bool axis_u = fabs(rv.eu[a]) >= fabs(rv.ev[a]);
+            if (elongated && long_u != axis_u) lw = 6 - lw0;
+        }
+        rv.tile_w_log2 = lw;
         g.views.push_back(rv);
+        const int tw = 1 << lw, th = 64 >> lw;
         const int ntx = (rv.width + tw - 1) / tw, nty = (rv.height + th - 1) / th;
         for (int ty = 0; ty < nty; ty++)
             for (int tx = 0; tx < ntx; tx++) {
@@ -634,14 +660,28 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             }
     }
     for (Group &g : groups) {
-        g.tile_w_log2 = (uint32_t)lw;
-        if (tun.order == 1) {
+        if (tun.order == 2) {
+            // Z-order (Morton) of the tile coordinates inside each view: tiles
+            // that are close in the queue form compact 2D patches
+            auto morton = [](uint32_t x, uint32_t y) {
+                uint64_t k = 0;
+                for (int b = 0; b < 16; b++)
+                    k |= (uint64_t)((x >> b) & 1u) << (2 * b) | (uint64_t)((y >> b) & 1u) << (2 * b + 1);
+                return k;
+            };
+            std::stable_sort(g.tiles.begin(), g.tiles.end(), [&](const Tile &a, const Tile &b) {
+                if (a.view != b.view) return a.view < b.view;
+                return morton(a.tx, a.ty) < morton(b.tx, b.ty);
+            });
+        } else if (tun.order == 1) {
             // longest estimated tile first; the queue chunks interleave so each
             // XCD's chunk also runs longest first
             std::vector<std::pair<double, uint32_t>> cost(g.tiles.size());
             for (size_t k = 0; k < g.tiles.size(); k++) {
                 const Tile &t = g.tiles[k];
-                cost[k] = {tile_cost(g.views[t.view], t.tx, t.ty, tw, th), (uint32_t)k};
+                const RayView &tv = g.views[t.view];
+                cost[k] = {tile_cost(tv, t.tx, t.ty, 1 << tv.tile_w_log2, 64 >> tv.tile_w_log2),
+                           (uint32_t)k};
             }
             std::stable_sort(cost.begin(), cost.end(),
                              [](const std::pair<double, uint32_t> &a,
@@ -687,7 +727,6 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
         bl.n_tiles = (uint32_t)g.tiles.size();
         bl.head = (uint32_t *)(acc + 2 * (size_t)n + 4 * gi);
         bl.n_queues = g.n_queues;
-        bl.tile_w_log2 = g.tile_w_log2;
         bl.flux_acc = (double *)acc;
         bl.step_acc = acc + n;
         e = launch_batch(g.store, g.f64, bl, blocks, stream);
@@ -871,14 +910,31 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
     (void)hipEventCreate(&e1);
     const dart_tuning saved = tuning_for(nullptr);
     std::vector<dart_tuning> cands;
-    const int shapes[][2] = {{8, 8}, {16, 4}, {4, 16}};
-    const int waves[] = {8, 16, 24, 32};
+    // Measured on MI355X: the L2 working set of the resident waves dominates,
+    // so the sweep covers low occupancies, row-like tiles and both spatial orders.
+    const int shapes[][2] = {{64, 1}, {32, 2}, {16, 4}, {8, 8}};
+    const int waves[] = {8, 12, 16};
+    const int orders[] = {0, 2};
     for (auto &sh : shapes)
         for (int w : waves)
-            for (int order = 0; order < 2; order++) cands.push_back({sh[0], sh[1], w, order});
+            for (int order : orders)
+                for (int orient = 0; orient < 2; orient++)
+                    cands.push_back({sh[0], sh[1], w, order, orient});
+    // Brick candidates: every power-of-two shape holding one 128-B cache line
+    // of records.  Which one wins depends on the view set: lines that extend
+    // along the rays' directions are used whole by one ray, lines across the
+    // image plane are only partly covered when rays are sparser than cells.
     std::vector<std::array<int, 3>> bricks;
-    if (rebrick) bricks = {{4, 4, 4}, {8, 8, 8}, {2, 2, 2}, {8, 8, 2}, {16, 16, 1}};
-    else bricks = {{0, 0, 0}};
+    if (rebrick) {
+        const int per_line = std::max(1u, 128u / record_bytes(stacks[0]->dev.store));
+        for (int bx = 1; bx <= per_line; bx *= 2)
+            for (int by = 1; bx * by <= per_line; by *= 2) {
+                const int bz = per_line / (bx * by);
+                if (bx * by * bz == per_line && bz <= 16) bricks.push_back({bx, by, bz});
+            }
+    } else {
+        bricks = {{0, 0, 0}};
+    }
     double best_ms = INFINITY;
     dart_tuning best = saved;
     std::array<int, 3> best_brick = {0, 0, 0};
