@@ -46,19 +46,34 @@ def pct(xs, q):
 
 # --------------------------------------------------------------------------- helpers
 
-def make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage, keep_host):
+def host_copy(j_dev, b_dev, kind):
+    """Host copy of device float32 fields in the oracle's encoding for a stack
+    stored as `kind` (float32, binary16, or bfloat16 bit patterns), converted
+    one epoch at a time."""
+    import synth
+    if kind == "f32":
+        return j_dev.cpu().numpy(), b_dev.cpu().numpy()
+    dt = np.float16 if kind == "f16" else np.uint16
+    conv = synth.to_f16 if kind == "f16" else synth.to_bf16_bits
+    jh = np.empty(tuple(j_dev.shape), dtype=dt)
+    bh = np.empty(tuple(b_dev.shape), dtype=dt)
+    for m in range(j_dev.shape[0]):
+        jh[m] = conv(j_dev[m].cpu().numpy())
+        bh[m] = conv(b_dev[m].cpu().numpy())
+    return jh, bh
+
+
+def make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage, kind, keep_host):
     import synth
     t0 = time.time()
     j, b, times = synth.jet_torch(dims, n_epochs, seed, gamma_spine=gamma, n_knots=knots)
     torch.cuda.synchronize()
-    host = None
-    if keep_host:
-        host = (j.cpu().numpy(), b.cpu().numpy())
+    host = host_copy(j, b, kind) if keep_host else None
     st = dart.dart_load_epochs(dims, (1.0, 1.0, 1.0), times, j, b, storage)
     torch.cuda.synchronize()
     del j, b
     torch.cuda.empty_cache()
-    log(f"stack {dims} x {n_epochs} epochs generated and loaded in {time.time() - t0:.1f} s")
+    log(f"stack {dims} x {n_epochs} epochs ({kind}) generated and loaded in {time.time() - t0:.1f} s")
     return st, times, host
 
 
@@ -98,12 +113,12 @@ def bandwidth_probe(dart, torch, stream, nbytes=4 << 30, reps=10):
     return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
 
 
-def oracle_sample(host, times, views, n_rays, seed, threads):
+def oracle_sample(host, times, views, n_rays, seed, threads, kind="f32"):
     """Runs the FP64 oracle on n_rays random pixels spread over the views.
     Returns (per-view list of (pixels, values), total cell-steps, seconds)."""
     import oracle
     j, b = host
-    ost = oracle.Stack(j, b, times)
+    ost = oracle.Stack(j, b, times, encoding=kind)
     rng = np.random.default_rng(seed)
     out, steps, secs = [], 0, 0.0
     per_view = max(1, n_rays // len(views))
@@ -128,11 +143,11 @@ def pix_err(got, ref, img_max):
 # --------------------------------------------------------------------------- workloads
 
 def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_spec, gamma,
-                        knots, seed, rec_bytes, dtype_name):
+                        knots, seed, rec_bytes, dtype_name, check_views=None, tune_views=None):
     stream = torch.cuda.Stream()
     keep_host = not args.no_cpu_baseline or args.check
     st, times, host = make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage,
-                                     keep_host)
+                                     dtype_name, keep_host)
     L = math.sqrt(sum(float(d) ** 2 for d in dims))
     views = [dart.View(th, ph, P, P, L / P, 0.0, alpha) for th, ph, P, alpha in views_spec]
     imgs = [torch.zeros((v.height, v.width), dtype=torch.float32, device="cuda") for v in views]
@@ -149,7 +164,8 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
         log(f"fixed tuning: {tuning}")
     elif args.autotune:
         t0 = time.time()
-        best, ms = dart.dart_autotune(stacks, views, rebrick=args.rebrick, stream=stream)
+        tv = views if tune_views is None else views[:tune_views]
+        best, ms = dart.dart_autotune([st] * len(tv), tv, rebrick=args.rebrick, stream=stream)
         info = dart.dart_stack_get_info(st)
         tuning = {"tile": [best.tile_w, best.tile_h], "waves_per_cu": best.waves_per_cu,
                   "order": best.order, "orient": best.orient, "brick": list(info.brick),
@@ -192,8 +208,8 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
 
     # accuracy on sampled pixels against the FP64 oracle (dequantised inputs)
     if args.check and host is not None:
-        jq, bq = dequantised(host, dtype_name)
-        samp, _, _ = oracle_sample((jq, bq), times, views, args.check_rays, 7, None)
+        cv = views if check_views is None else views[:check_views]
+        samp, _, _ = oracle_sample(host, times, cv, args.check_rays, 7, None, dtype_name)
         errs = []
         for (pix, val), im in zip(samp, imgs):
             g = im.cpu().numpy()
@@ -205,12 +221,11 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
 
     cpu = None
     if not args.no_cpu_baseline and host is not None:
-        jq, bq = dequantised(host, dtype_name)
         threads = os.cpu_count() or 1
         # calibrate on a small sample, then size the sample for ~10-20 s
-        _, n0, s0 = oracle_sample((jq, bq), times, views, 256 * n_img, 11, threads)
-        rays = int(min(1 << 20, max(256 * n_img, 256 * n_img * 12.0 / max(s0, 1e-3))))
-        _, n1, s1 = oracle_sample((jq, bq), times, views, rays, 12, threads)
+        _, n0, s0 = oracle_sample(host, times, views, 64 * n_img, 11, threads, dtype_name)
+        rays = int(min(1 << 22, max(64 * n_img, 64 * n_img * 12.0 / max(s0, 1e-3))))
+        _, n1, s1 = oracle_sample(host, times, views, rays, 12, threads, dtype_name)
         cpu = {"value": n1 / s1, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{rays} random pixels over the {n_img} views ({n1} cell-steps, {s1:.1f} s)",
                "images_per_s_equiv": (n1 / s1) / (cell_steps / n_img)}
@@ -254,13 +269,129 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
     return line
 
 
-def dequantised(host, dtype_name):
+def build_stack_incremental(dart, torch, dims, n_epochs, seed, gamma, knots, storage,
+                            chunk_bytes=8 << 30):
+    """Creates a stack and fills it a few epochs at a time from device-generated
+    float32 fields (the two-phase load for stacks too large to stage whole)."""
     import synth
-    j, b = host
-    if dtype_name == "f32":
-        return j, b
-    f = synth.round_f16 if dtype_name == "f16" else synth.round_bf16
-    return f(j), f(b)
+    times = synth.jet_times(dims, n_epochs)
+    st = dart.dart_stack_create(dims, (1.0, 1.0, 1.0), times, storage)
+    nx, ny, nz = dims
+    per_epoch = nx * ny * nz * 16
+    chunk = max(1, min(n_epochs, chunk_bytes // per_epoch))
+    params = synth.jet_params(dims, seed, gamma_spine=gamma, n_knots=knots)
+    stream = torch.cuda.current_stream()
+    jbuf = torch.empty((chunk, nz, ny, nx), dtype=torch.float32, device="cuda")
+    bbuf = torch.empty((chunk, nz, ny, nx, 3), dtype=torch.float32, device="cuda")
+    for m0 in range(0, n_epochs, chunk):
+        c = min(chunk, n_epochs - m0)
+        synth.jet_fill_device(params, times[m0:m0 + c], jbuf.data_ptr(), bbuf.data_ptr(),
+                              stream.cuda_stream)
+        dart.dart_stack_set_epochs(st, m0, jbuf[:c], bbuf[:c], stream=stream)
+    torch.cuda.synchronize()
+    del jbuf, bbuf
+    torch.cuda.empty_cache()
+    return st, times
+
+
+def run_serve_workload(args, dart, torch):
+    """Poisson request stream on resident FP16 stacks through the server."""
+    import synth
+    rng = np.random.default_rng(1004)
+    specs = [(128, 8), (128, 32), (256, 16), (256, 32), (512, 8), (512, 32)]
+    stacks = []
+    t0 = time.time()
+    for k, (n, M) in enumerate(specs):
+        gamma = float(rng.uniform(2.0, 5.0))
+        st, _ = build_stack_incremental(dart, torch, (n, n, n), M, 2000 + k, gamma, 4,
+                                        dart.DART_F16)
+        stacks.append((st, n, M))
+    resident = sum(dart.dart_stack_get_info(s).device_bytes for s, _, _ in stacks)
+    log(f"{len(stacks)} FP16 stacks resident ({resident / 1e9:.1f} GB) in {time.time() - t0:.1f} s")
+    n_req, warm, rate = args.requests, args.serve_warmup, args.rate
+    sizes = (128, 256, 512, 1024)
+    reqs = []
+    for q in range(n_req):
+        s, n, M = stacks[int(rng.integers(0, len(stacks)))]
+        P = int(rng.choice(sizes))
+        th = math.degrees(math.acos(rng.uniform(-1.0, 1.0)))
+        reqs.append((s, dart.View(th, float(rng.uniform(0, 360)), P, P,
+                                  math.sqrt(3.0) * n / P, 0.0, float(rng.uniform(0.5, 1.0)))))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    pool = {P: [torch.empty((P, P), dtype=torch.float32, device="cuda") for _ in range(48)]
+            for P in sizes}
+    owner = {}
+    srv = dart.dart_server_create(args.budget_gb << 30, max_inflight=512, n_streams=3)
+
+    def stream_run(arr):
+        tickets, results = [], {}
+        start = time.perf_counter()
+        for q, (s, v) in enumerate(reqs[:len(arr)]):
+            slot = (v.width, q % 48)
+            if slot in owner and owner[slot] not in results:
+                results[owner[slot]] = dart.dart_wait(srv, owner[slot])
+            delay = start + arr[q] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            t = dart.dart_submit(srv, s, v, pool[v.width][q % 48])
+            owner[slot] = t
+            tickets.append(t)
+        for t in tickets:
+            if t not in results:
+                results[t] = dart.dart_wait(srv, t)
+        return tickets, results, time.perf_counter() - start
+
+    tickets, results, wall = stream_run(arrivals)
+    lat = np.array([results[t][2] for t in tickets[warm:]])
+    steps_served = sum(results[t][1] for t in tickets[warm:])
+    span = arrivals[-1] - arrivals[warm]
+    log(f"served {n_req} requests at {rate}/s: p50 {np.percentile(lat, 50):.2f} ms, "
+        f"p99 {np.percentile(lat, 99):.2f} ms")
+    stats = dart.dart_server_get_stats(srv)
+    # saturation: every request offered at once
+    owner.clear()
+    sat_n = min(1000, n_req)
+    tk, res, sat_wall = stream_run(np.zeros(sat_n))
+    sat_steps = sum(res[t][1] for t in tk)
+    dart.dart_server_destroy(srv)
+    # plain kernel, one request after the other, on the same requests
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for q, (s, v) in enumerate(reqs[:sat_n]):
+        dart.dart_render(s, v, pool[v.width][q % 48], stream=stream, stats=False)
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - p0
+    # each served result equals its solo render (sampled requests)
+    same = True
+    for q in rng.choice(sat_n, size=min(32, sat_n), replace=False):
+        s, v = reqs[q]
+        a = torch.zeros((v.height, v.width), dtype=torch.float32, device="cuda")
+        b = torch.zeros_like(a)
+        srv2 = dart.dart_server_create(1 << 30, 4, 1)
+        dart.dart_wait(srv2, dart.dart_submit(srv2, s, v, a))
+        dart.dart_server_destroy(srv2)
+        dart.dart_render(s, v, b, stats=False)
+        torch.cuda.synchronize()
+        same &= bool(torch.equal(a, b))
+    return {
+        "metric": "cell-steps/s & images/s (batched vs plain kernel) at 1e-5 rel; p50/p99 ms",
+        "value": sat_steps / sat_wall, "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": n_req, "warmup": warm, "ms_per_step": 1e3 * sat_wall / sat_n,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": "served stream: Poisson %g req/s over 6 resident FP16 jet stacks "
+                               "(128^3..512^3, 8-32 epochs), images 128^2..1024^2" % rate,
+                   "requests": n_req, "resident_gb": resident / 1e9, "budget_gb": args.budget_gb},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "offered_req_per_s": rate, "served_req_per_s": (n_req - warm) / max(span, 1e-9),
+        "served_cell_steps_per_s": steps_served / max(span, 1e-9),
+        "saturation_images_per_s": sat_n / sat_wall,
+        "plain_images_per_s": sat_n / plain_wall,
+        "speedup_images_per_s_vs_plain": plain_wall / sat_wall,
+        "waves": int(stats.waves), "max_wave_requests": int(stats.max_wave_requests),
+        "served_equals_solo": same,
+    }
 
 
 # --------------------------------------------------------------------------- main
@@ -270,7 +401,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="jet", choices=["jet"])
+    ap.add_argument("--workload", default="jet", choices=["jet", "batch", "serve"])
+    ap.add_argument("--storage", default="f16", choices=["f16", "bf16"],
+                    help="batch workload: 16-bit storage type")
+    ap.add_argument("--requests", type=int, default=6000)
+    ap.add_argument("--serve-warmup", type=int, default=500)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--budget-gb", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", default=True)
     ap.add_argument("--no-check", dest="check", action="store_false")
@@ -301,6 +438,16 @@ def main():
         line = run_render_workload(
             args, dart, torch, "jet 256x256x512, 16 epochs, FP32, 4 views 512^2 (theta 10/30/60/90)",
             (256, 256, 512), 16, dart.DART_F32, views, 5.0, 4, 2, 16, "f32")
+    elif args.workload == "batch":
+        import synth
+        views = [(th, ph, P, 0.6) for th, ph, P in synth.isotropic_views(64, 1003)]
+        storage = dart.DART_F16 if args.storage == "f16" else dart.DART_BF16
+        line = run_render_workload(
+            args, dart, torch, f"uneven batch 384^3, 32 epochs, {args.storage.upper()}, 64 isotropic "
+            "views, sides in {128,256,512,1024}", (384, 384, 384), 32, storage, views, 5.0, 4, 3, 8,
+            args.storage, check_views=8, tune_views=16)
+    else:
+        line = run_serve_workload(args, dart, torch)
     print(json.dumps(line), flush=True)
 
 

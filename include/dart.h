@@ -69,9 +69,9 @@ typedef enum { DART_F64 = 0, DART_F32 = 1, DART_F16 = 2, DART_BF16 = 3 } dart_dt
 #define DART_NO_BEAMING 0x2u    /* routine A: D = 1 */
 #define DART_NEAREST_EPOCH 0x4u /* weight 1 on the epoch closest to tbar (ties: earlier) */
 #define DART_NO_KAHAN 0x8u      /* plain (uncompensated) FP32 accumulation */
-#define DART_FORCE_F64_DDA 0x10u /* FP64 ray parameters (DDA crossings, retarded times) even
-                                    for 16/32-bit stacks; chosen by itself when a ray may
-                                    cross more than 4096 cells */
+#define DART_FORCE_F64_DDA 0x10u /* FP64 ray parameters (DDA crossings, retarded times) for
+                                    16-bit stacks too; FP64 and FP32 stacks always use them,
+                                    16-bit stacks when a ray may cross more than 4096 cells */
 #define DART_DEVICE_PTRS 0x20u  /* load: field pointers are device pointers;
                                    view: the image pointer is a device pointer */
 #define DART_KERNEL_PLAIN 0x40u /* dart_render_batch: force the one-launch-per-image kernel */
@@ -214,13 +214,16 @@ dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t bytes, int
  * on several streams and overlap on the device.  Output images are staged in
  * server-owned device memory; admission waits until the staged images of the
  * requests in flight fit in hbm_budget_bytes and fewer than max_inflight are
- * running.
+ * admitted.  Wave descriptors live in per-stream buffers fixed at creation
+ * (budget / 4, clamped to [4, 64] MiB per stream, outside the budget); a wave
+ * takes admitted requests in arrival order while their descriptors fit.
  *   image      destination [height][width] float32 (host memory, or device
  *              memory with DART_DEVICE_PTRS in the view flags); must stay valid
  *              until the ticket completes.
  *   ticket     out: identifies the request.
- * dart_poll: done = 1 once the image is written; flux and latency (ms from
- * submission to completion) are then valid.  dart_wait blocks until done.
+ * dart_poll: done = 1 once the image is written; flux, cell-steps and latency
+ * (ms from submission to completion) are then valid, and the ticket is
+ * retired.  dart_wait blocks until done.  flux, steps, latency_ms are nullable.
  * dart_server_destroy waits for every request.
  */
 dart_status dart_server_create(size_t hbm_budget_bytes, int32_t max_inflight, int32_t n_streams,
@@ -228,15 +231,16 @@ dart_status dart_server_create(size_t hbm_budget_bytes, int32_t max_inflight, in
 dart_status dart_submit(dart_server *srv, const dart_stack *s, const dart_view *v, void *image,
                         uint64_t *ticket);
 dart_status dart_poll(dart_server *srv, uint64_t ticket, int32_t *done, double *flux,
+                      uint64_t *steps, double *latency_ms);
+dart_status dart_wait(dart_server *srv, uint64_t ticket, double *flux, uint64_t *steps,
                       double *latency_ms);
-dart_status dart_wait(dart_server *srv, uint64_t ticket, double *flux, double *latency_ms);
 dart_status dart_server_destroy(dart_server *srv);
 
 typedef struct {
     uint64_t submitted, completed, waves;
     uint64_t max_wave_requests;
     uint64_t bytes_in_use, bytes_peak;
-    uint64_t admission_waits;  /* times a request waited for memory or a slot */
+    uint64_t admission_waits;  /* requests that had to wait for memory or a slot */
 } dart_server_stats;
 dart_status dart_server_get_stats(dart_server *srv, dart_server_stats *st);
 

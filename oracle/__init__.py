@@ -92,6 +92,12 @@ def _load():
         lib.orc_count_blocks.restype = ctypes.c_longlong
         lib.orc_count_blocks.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View), ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int]
+        lib.orc_render_window.restype = ctypes.c_int
+        lib.orc_render_window.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View), ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
+                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
+                                          ctypes.c_int]
         lib.orc_camera_basis.restype = None
         lib.orc_camera_basis.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View),
                                          ctypes.c_void_p]
@@ -99,16 +105,26 @@ def _load():
     return _lib
 
 
+_DT_CODE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+
+
 @dataclass
 class Stack:
-    """Epoch stack in the caller's layout: j [M][nz][ny][nx], beta [M][nz][ny][nx][3]."""
+    """Epoch stack in the caller's layout: j [M][nz][ny][nx], beta [M][nz][ny][nx][3].
+
+    Arrays may be float64, float32, float16, or uint16 holding bfloat16 bit
+    patterns (encoding="bf16"); the oracle widens every value to FP64 itself."""
     j: np.ndarray
     beta: np.ndarray
     times: np.ndarray
     cell: tuple = (1.0, 1.0, 1.0)
+    encoding: str = None
 
     def __post_init__(self):
-        dt = np.float32 if self.j.dtype == np.float32 else np.float64
+        if self.encoding is None:
+            self.encoding = {np.dtype(np.float32): "f32", np.dtype(np.float16): "f16",
+                             np.dtype(np.uint16): "bf16"}.get(np.dtype(self.j.dtype), "f64")
+        dt = {"f64": np.float64, "f32": np.float32, "f16": np.float16, "bf16": np.uint16}[self.encoding]
         self.j = np.ascontiguousarray(self.j, dtype=dt)
         self.beta = np.ascontiguousarray(self.beta, dtype=dt)
         self.times = np.ascontiguousarray(self.times, dtype=np.float64)
@@ -128,7 +144,7 @@ class Stack:
         g.cell[:] = [float(c) for c in self.cell]
         g.n_epochs = self.j.shape[0]
         g.times = self.times.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        g.dtype = 1 if self.j.dtype == np.float32 else 0
+        g.dtype = _DT_CODE[self.encoding]
         g.j = self.j.ctypes.data
         g.beta = self.beta.ctypes.data
         return g
@@ -185,6 +201,65 @@ def render(stack: Stack, view: View, pixels=None, threads=None):
 def render_brute(stack: Stack, view: View, pixels=None, threads=None):
     """O2: per-cell box test against every cell (tiny grids only)."""
     return _run("orc_render_brute", stack, view, pixels, threads)
+
+
+def render_window(times, j_sub, beta_sub, e0, view: View, t_lo, t_hi, hi_closed, out,
+                  pixels=None, cell=(1.0, 1.0, 1.0), encoding=None, threads=None):
+    """Snapshot-outer O1: ``j_sub``/``beta_sub`` hold epochs [e0, e0 + n) of a
+    stack whose epoch times are ``times`` (all M); ADDS to ``out`` the cells
+    whose retarded time lies in [t_lo, t_hi) ([t_lo, t_hi] if hi_closed).
+    Returns the cell-steps of the interval."""
+    lib = _load()
+    sub = Stack(j_sub, beta_sub, np.zeros(j_sub.shape[0]), cell=cell, encoding=encoding)
+    g = sub._cgrid()
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    g.n_epochs = len(t)
+    g.times = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if pixels is None:
+        assert out.shape == (view.height, view.width) and out.dtype == np.float64
+        pix_ptr, n = None, view.width * view.height
+    else:
+        pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int32).reshape(-1, 2))
+        assert out.shape == (pix.shape[0],) and out.dtype == np.float64
+        pix_ptr, n = pix.ctypes.data, pix.shape[0]
+    steps = ctypes.c_longlong(0)
+    rc = lib.orc_render_window(ctypes.byref(g), ctypes.byref(view._cview()), int(e0),
+                               int(j_sub.shape[0]), float(t_lo), float(t_hi), int(hi_closed),
+                               pix_ptr, n, out.ctypes.data, ctypes.byref(steps), _threads(threads))
+    if rc != 0:
+        raise ValueError(f"oracle window render failed (rc={rc})")
+    return int(steps.value)
+
+
+def render_streamed(times, epoch_loader, view: View, pixels=None, cell=(1.0, 1.0, 1.0),
+                    encoding=None, threads=None):
+    """Whole image (or pixel list) by the snapshot-outer form: for every
+    interval [t_m, t_{m+1}) the caller's ``epoch_loader(m)`` returns
+    (j_sub, beta_sub) for epochs m and m+1.  Two epochs are held at a time."""
+    t = np.asarray(times, dtype=np.float64)
+    M = len(t)
+    if pixels is None:
+        out = np.zeros((view.height, view.width))
+    else:
+        out = np.zeros(np.asarray(pixels).reshape(-1, 2).shape[0])
+    steps = 0
+    if view.flags & NO_LOOKBACK:
+        # one epoch interval holds t_obs
+        if not (t[0] <= view.t_obs <= t[-1]):
+            return out, 0
+        m = 0 if M == 1 else min(int(np.searchsorted(t, view.t_obs, side="right")) - 1, M - 2)
+        js, bs = epoch_loader(m)
+        steps += render_window(t, js, bs, m, view, -np.inf, np.inf, 1, out, pixels, cell, encoding, threads)
+        return out, steps
+    if M == 1:
+        js, bs = epoch_loader(0)
+        steps += render_window(t, js, bs, 0, view, t[0], t[0], 1, out, pixels, cell, encoding, threads)
+        return out, steps
+    for m in range(M - 1):
+        js, bs = epoch_loader(m)
+        steps += render_window(t, js, bs, m, view, t[m], t[m + 1], int(m == M - 2), out, pixels,
+                               cell, encoding, threads)
+    return out, steps
 
 
 def flux(image: np.ndarray, view: View) -> float:

@@ -48,6 +48,8 @@
 
 #define ORC_DT_F64 0
 #define ORC_DT_F32 1
+#define ORC_DT_F16 2  /* IEEE binary16 bit patterns (uint16) */
+#define ORC_DT_BF16 3 /* bfloat16 bit patterns (uint16): the top half of a binary32 */
 
 typedef struct {
     int n[3];             /* cells along x, y, z */
@@ -82,8 +84,26 @@ static void sincos_deg(double deg, double *s, double *c) {
     *c = cos(deg * (M_PI / 180.0));
 }
 
+/* binary16 -> double from the bit fields: sign, 5-bit exponent (bias 15),
+ * 10-bit fraction; subnormals scale the fraction by 2^-24 */
+static double half_to_double(uint16_t h) {
+    int sign = h >> 15, ex = (h >> 10) & 31, fr = h & 1023;
+    double v;
+    if (ex == 0) v = ldexp((double)fr, -24);
+    else if (ex == 31) v = fr ? NAN : INFINITY;
+    else v = ldexp(1.0 + fr / 1024.0, ex - 15);
+    return sign ? -v : v;
+}
+
 static double load_val(const void *p, int dtype, size_t idx) {
     if (dtype == ORC_DT_F32) return (double)((const float *)p)[idx];
+    if (dtype == ORC_DT_F16) return half_to_double(((const uint16_t *)p)[idx]);
+    if (dtype == ORC_DT_BF16) {
+        uint32_t u = (uint32_t)((const uint16_t *)p)[idx] << 16;
+        float f;
+        memcpy(&f, &u, sizeof(f));
+        return (double)f;
+    }
     return ((const double *)p)[idx];
 }
 
@@ -170,6 +190,19 @@ static double doppler_pow(const double beta[3], const double shat[3], double p) 
     return pow(D, p);
 }
 
+/* Epoch-interval restriction for the snapshot-outer form: only the epochs
+ * [e0, e0 + ne) are present in the grid's arrays, and only cells whose
+ * retarded time lies in [t_lo, t_hi) (closed at t_hi when hi_closed) are
+ * summed.  The default (ne = 0) means every epoch is present and no
+ * restriction applies. */
+typedef struct {
+    int e0, ne;
+    double t_lo, t_hi;
+    int hi_closed;
+} orc_window;
+
+static __thread const orc_window *tl_win = NULL;
+
 /* Contribution of one chord [sa, sb] inside cell (ix, iy, iz).  Returns 1 when
  * the cell lies inside the temporal window (a counted cell-step). */
 static int cell_term(const orc_grid *g, const orc_view *v, const double shat[3], int ix,
@@ -177,6 +210,10 @@ static int cell_term(const orc_grid *g, const orc_view *v, const double shat[3],
     double ds = sb - sa;
     double smid = 0.5 * (sa + sb);
     double tbar = (v->flags & ORC_NO_LOOKBACK) ? v->t_obs : v->t_obs - smid;
+    const orc_window *w = tl_win;
+    if (w && w->ne > 0) {
+        if (!(tbar >= w->t_lo && (tbar < w->t_hi || (w->hi_closed && tbar == w->t_hi)))) return 0;
+    }
     int ms[2];
     double ws[2];
     int k = orc_epoch_weights(g->times, g->n_epochs, tbar, v->flags, ms, ws);
@@ -187,7 +224,12 @@ static int cell_term(const orc_grid *g, const orc_view *v, const double shat[3],
     double sum = 0.0;
     for (int q = 0; q < k; q++) {
         if (ws[q] == 0.0) continue;
-        size_t r = (size_t)ms[q] * ncell + c;
+        int me = ms[q];
+        if (w && w->ne > 0) {
+            me -= w->e0;
+            if (me < 0 || me >= w->ne) return -1; /* the caller did not load this epoch */
+        }
+        size_t r = (size_t)me * ncell + c;
         double jv = load_val(g->j, g->dtype, r);
         double dp = 1.0;
         if (!(v->flags & ORC_NO_BEAMING)) {
@@ -206,6 +248,28 @@ static int cmp_double(const void *a, const void *b) {
     return (x > y) - (x < y);
 }
 
+static __thread int tl_err = 0;
+
+/* Appends the crossings of the planes x_a = k dx_a (0 < k < n_a) that lie
+ * strictly inside (s0, s1); only the k whose plane can be reached in that
+ * range are visited. */
+static int add_crossings(const orc_grid *g, const double o[3], const double d[3], double s0,
+                         double s1, double *out, int cnt) {
+    for (int a = 0; a < 3; a++) {
+        if (d[a] == 0.0) continue;
+        double x0 = (o[a] + s0 * d[a]) / g->cell[a], x1 = (o[a] + s1 * d[a]) / g->cell[a];
+        if (x0 > x1) { double t = x0; x0 = x1; x1 = t; }
+        long k0 = (long)floor(x0) - 1, k1 = (long)ceil(x1) + 1;
+        if (k0 < 1) k0 = 1;
+        if (k1 > g->n[a] - 1) k1 = g->n[a] - 1;
+        for (long k = k0; k <= k1; k++) {
+            double s = (k * g->cell[a] - o[a]) / d[a];
+            if (s > s0 && s < s1) out[cnt++] = s;
+        }
+    }
+    return cnt;
+}
+
 /* O1: one pixel by sorted plane crossings */
 static double ray_sorted(const orc_grid *g, const orc_view *v, const orc_camera *cam, int i,
                          int j, long long *steps, double *scratch) {
@@ -216,16 +280,23 @@ static double ray_sorted(const orc_grid *g, const orc_view *v, const orc_camera 
     for (int a = 0; a < 3; a++) hi[a] = g->n[a] * g->cell[a];
     double s_in, s_out;
     if (!ray_box(o, d, lo, hi, &s_in, &s_out)) return 0.0;
+    const orc_window *w = tl_win;
+    if (w && w->ne > 0 && !(v->flags & ORC_NO_LOOKBACK)) {
+        /* snapshot-outer form: only chords whose midpoint can fall inside the
+         * window are needed; a margin of one cell diagonal keeps every such
+         * chord whole, and the partial chords at the clipped ends have their
+         * midpoints outside the window */
+        double diag = sqrt(g->cell[0] * g->cell[0] + g->cell[1] * g->cell[1] +
+                           g->cell[2] * g->cell[2]);
+        double c0 = v->t_obs - w->t_hi - diag, c1 = v->t_obs - w->t_lo + diag;
+        if (c0 > s_in) s_in = c0;
+        if (c1 < s_out) s_out = c1;
+        if (!(s_out > s_in)) return 0.0;
+    }
     int cnt = 0;
     scratch[cnt++] = s_in;
     scratch[cnt++] = s_out;
-    for (int a = 0; a < 3; a++) {
-        if (d[a] == 0.0) continue;
-        for (int k = 1; k < g->n[a]; k++) {
-            double s = (k * g->cell[a] - o[a]) / d[a];
-            if (s > s_in && s < s_out) scratch[cnt++] = s;
-        }
-    }
+    cnt = add_crossings(g, o, d, s_in, s_out, scratch, cnt);
     qsort(scratch, (size_t)cnt, sizeof(double), cmp_double);
     double acc = 0.0;
     long long n_steps = 0;
@@ -239,7 +310,9 @@ static double ray_sorted(const orc_grid *g, const orc_view *v, const orc_camera 
             if (idx[a] < 0 || idx[a] >= g->n[a]) inside = 0;
         }
         if (!inside) continue;
-        n_steps += cell_term(g, v, d, idx[0], idx[1], idx[2], sa, sb, &acc);
+        int r = cell_term(g, v, d, idx[0], idx[1], idx[2], sa, sb, &acc);
+        if (r < 0) tl_err = 1;
+        else n_steps += r;
     }
     if (steps) *steps += n_steps;
     return acc;
@@ -260,7 +333,9 @@ static double ray_brute(const orc_grid *g, const orc_view *v, const orc_camera *
                 double hi[3] = {(ix + 1) * g->cell[0], (iy + 1) * g->cell[1], (iz + 1) * g->cell[2]};
                 double sa, sb;
                 if (!ray_box(o, d, lo, hi, &sa, &sb)) continue;
-                n_steps += cell_term(g, v, d, ix, iy, iz, sa, sb, &acc);
+                int r = cell_term(g, v, d, ix, iy, iz, sa, sb, &acc);
+                if (r < 0) tl_err = 1;
+                else n_steps += r;
             }
     if (steps) *steps += n_steps;
     return acc;
@@ -277,26 +352,35 @@ typedef struct {
     double *out;
     long long steps;
     int tid, nthreads, brute;
+    const orc_window *win;
+    int accumulate, err;
 } orc_job;
 
 static void *worker(void *arg) {
     orc_job *jb = (orc_job *)arg;
     const orc_grid *g = jb->g;
+    tl_win = jb->win;
+    tl_err = 0;
     size_t cap = 2 + (size_t)g->n[0] + g->n[1] + g->n[2];
     double *scratch = (double *)malloc(cap * sizeof(double));
     for (long long q = jb->tid; q < jb->n_pix; q += jb->nthreads) {
         int i, j;
         if (jb->pix) { i = jb->pix[2 * q]; j = jb->pix[2 * q + 1]; }
         else { i = (int)(q % jb->v->width); j = (int)(q / jb->v->width); }
-        jb->out[q] = jb->brute ? ray_brute(g, jb->v, jb->cam, i, j, &jb->steps)
+        double val = jb->brute ? ray_brute(g, jb->v, jb->cam, i, j, &jb->steps)
                                : ray_sorted(g, jb->v, jb->cam, i, j, &jb->steps, scratch);
+        if (jb->accumulate) jb->out[q] += val;
+        else jb->out[q] = val;
     }
     free(scratch);
+    jb->err = tl_err;
+    tl_win = NULL;
     return NULL;
 }
 
-static int run(const orc_grid *g, const orc_view *v, const int32_t *pix, long long n_pix,
-               double *out, long long *steps_out, int nthreads, int brute) {
+static int run_ex(const orc_grid *g, const orc_view *v, const int32_t *pix, long long n_pix,
+                  double *out, long long *steps_out, int nthreads, int brute,
+                  const orc_window *win, int accumulate) {
     if (!g || !v || !out || g->n_epochs < 1) return -1;
     for (int a = 0; a < 3; a++)
         if (g->n[a] < 1 || !(g->cell[a] > 0)) return -1;
@@ -309,20 +393,27 @@ static int run(const orc_grid *g, const orc_view *v, const int32_t *pix, long lo
     orc_job *jobs = (orc_job *)calloc((size_t)nthreads, sizeof(orc_job));
     pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
     for (int t = 0; t < nthreads; t++) {
-        orc_job jb = {g, v, &cam, pix, n_pix, out, 0, t, nthreads, brute};
+        orc_job jb = {g, v, &cam, pix, n_pix, out, 0, t, nthreads, brute, win, accumulate, 0};
         jobs[t] = jb;
         if (nthreads > 1) pthread_create(&th[t], NULL, worker, &jobs[t]);
     }
     if (nthreads == 1) worker(&jobs[0]);
     long long steps = 0;
+    int err = 0;
     for (int t = 0; t < nthreads; t++) {
         if (nthreads > 1) pthread_join(th[t], NULL);
         steps += jobs[t].steps;
+        err |= jobs[t].err;
     }
     if (steps_out) *steps_out = steps;
     free(jobs);
     free(th);
-    return 0;
+    return err ? -2 : 0;
+}
+
+static int run(const orc_grid *g, const orc_view *v, const int32_t *pix, long long n_pix,
+               double *out, long long *steps_out, int nthreads, int brute) {
+    return run_ex(g, v, pix, n_pix, out, steps_out, nthreads, brute, NULL, 0);
 }
 
 /* O1 over a pixel list (pix = (i, j) pairs) or over the whole image (pix = NULL,
@@ -331,6 +422,21 @@ static int run(const orc_grid *g, const orc_view *v, const int32_t *pix, long lo
 int orc_render(const orc_grid *g, const orc_view *v, const int32_t *pix, long long n_pix,
                double *out, long long *steps_out, int nthreads) {
     return run(g, v, pix, n_pix, out, steps_out, nthreads, 0);
+}
+
+/* Snapshot-outer form of O1 (the chronology of the paper's Fig. 5): the grid's
+ * arrays hold only epochs [e0, e0 + ne) (times still lists all M epochs), and
+ * the call ADDS to out[] the contributions of the cells whose retarded time
+ * lies in [t_lo, t_hi) (or [t_lo, t_hi] with hi_closed).  Summing the calls
+ * over the intervals [t_m, t_{m+1}) with epochs {m, m+1} loaded, the last one
+ * closed, gives the whole image while only two epochs are held at a time.
+ * Returns -2 when a cell in the interval needs an epoch that was not loaded. */
+int orc_render_window(const orc_grid *g, const orc_view *v, int e0, int ne, double t_lo,
+                      double t_hi, int hi_closed, const int32_t *pix, long long n_pix, double *out,
+                      long long *steps_out, int nthreads) {
+    if (ne < 1 || e0 < 0 || e0 + ne > g->n_epochs) return -1;
+    orc_window w = {e0, ne, t_lo, t_hi, hi_closed};
+    return run_ex(g, v, pix, n_pix, out, steps_out, nthreads, 0, &w, 1);
 }
 
 /* O2, same interface; cost grows with every cell of the grid per pixel */

@@ -408,8 +408,13 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     rv->t_obs = v->t_obs;
     rv->p = 2.0 + v->alpha;
     rv->flags = v->flags & (F_NO_LOOKBACK | F_NO_BEAMING | F_NEAREST | F_NO_KAHAN | F_F64_DDA);
-    // long rays: FP64 ray parameters when a ray may cross more than ~4k cells
-    if (s->dev.n[0] + s->dev.n[1] + s->dev.n[2] > 4096) rv->flags |= F_F64_DDA;
+    // FP64 ray parameters (plane crossings, chord midpoints) when a ray may
+    // cross more than ~4k cells, and for FP32 stacks: FP32 crossings of
+    // magnitude ~L/2 carry ~1e-5 absolute rounding, which chords at jumps of
+    // the emissivity (a jet surface) turn into ~1e-5 relative pixel errors,
+    // the size of the FP32 tolerance.  16-bit stacks keep FP32 crossings.
+    if (s->dev.n[0] + s->dev.n[1] + s->dev.n[2] > 4096 || s->dev.store == ST_F32)
+        rv->flags |= F_F64_DDA;
     rv->width = v->width;
     rv->height = v->height;
     rv->out_f64 = v->out_dtype == DART_F64;
@@ -935,54 +940,72 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
     } else {
         bricks = {{0, 0, 0}};
     }
-    double best_ms = INFINITY;
-    dart_tuning best = saved;
-    std::array<int, 3> best_brick = {0, 0, 0};
-    dart_status result = DART_OK;
-    for (auto &br : bricks) {
-        if (br[0]) {
-            for (int32_t i = 0; i < n; i++) {
-                bool seen = false;
-                for (int32_t k = 0; k < i; k++) seen |= stacks[k] == stacks[i];
-                if (seen) continue;
-                result = dart_stack_rebrick(stacks[i], br.data(), hip_stream);
-                if (result != DART_OK) break;
-            }
-            if (result != DART_OK) break;
+    // one warm-up call (plans and captures the graph), then the best of two replays
+    auto measure = [&](const dart_tuning &c, float *ms_out) -> dart_status {
+        for (int32_t i = 0; i < n; i++) {
+            stacks[i]->tuning = c;
+            stacks[i]->tuned = true;
         }
-        for (const dart_tuning &c : cands) {
-            for (int32_t i = 0; i < n; i++) {
-                stacks[i]->tuning = c;
-                stacks[i]->tuned = true;
-            }
-            // one warm-up (plans and captures), then timed replays
-            result = dart_render_batch(stacks, vv.data(), n, imgs.data(), nullptr, nullptr, hip_stream);
-            if (result != DART_OK) break;
-            float ms_min = INFINITY;
-            for (int rep = 0; rep < 3; rep++) {
-                (void)hipEventRecord(e0, stream);
-                result = dart_render_batch(stacks, vv.data(), n, imgs.data(), nullptr, nullptr, hip_stream);
-                (void)hipEventRecord(e1, stream);
-                (void)hipEventSynchronize(e1);
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                ms_min = std::min(ms_min, ms);
-            }
-            if (result != DART_OK) break;
-            if (ms_min < best_ms) {
-                best_ms = ms_min;
-                best = c;
-                best_brick = br;
-            }
+        dart_status r = dart_render_batch(stacks, vv.data(), n, imgs.data(), nullptr, nullptr, hip_stream);
+        if (r != DART_OK) return r;
+        float ms_min = INFINITY;
+        for (int rep = 0; rep < 2; rep++) {
+            (void)hipEventRecord(e0, stream);
+            r = dart_render_batch(stacks, vv.data(), n, imgs.data(), nullptr, nullptr, hip_stream);
+            (void)hipEventRecord(e1, stream);
+            (void)hipEventSynchronize(e1);
+            if (r != DART_OK) return r;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms_min = std::min(ms_min, ms);
         }
-        if (result != DART_OK) break;
-    }
-    if (result == DART_OK && best_brick[0] && rebrick) {
+        *ms_out = ms_min;
+        return DART_OK;
+    };
+    auto rebrick_all = [&](const std::array<int, 3> &br) -> dart_status {
         for (int32_t i = 0; i < n; i++) {
             bool seen = false;
             for (int32_t k = 0; k < i; k++) seen |= stacks[k] == stacks[i];
-            if (!seen) result = dart_stack_rebrick(stacks[i], best_brick.data(), hip_stream);
+            if (seen) continue;
+            dart_status r = dart_stack_rebrick(stacks[i], br.data(), hip_stream);
+            if (r != DART_OK) return r;
+        }
+        return DART_OK;
+    };
+    double best_ms = INFINITY;
+    dart_tuning best = saved;
+    dart_status result = DART_OK;
+    // Stage 1: brick shapes under a few representative launch shapes.
+    std::array<int, 3> best_brick = {0, 0, 0};
+    if (rebrick) {
+        const dart_tuning probes[] = {{64, 1, 12, 0, 0}, {64, 1, 12, 0, 1}, {8, 8, 12, 0, 0}};
+        for (auto &br : bricks) {
+            result = rebrick_all(br);
             if (result != DART_OK) break;
+            for (const dart_tuning &c : probes) {
+                float ms = 0;
+                result = measure(c, &ms);
+                if (result != DART_OK) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                    best_brick = br;
+                }
+            }
+            if (result != DART_OK) break;
+        }
+        if (result == DART_OK) result = rebrick_all(best_brick);
+    }
+    // Stage 2: launch shapes on the chosen layout.
+    if (result == DART_OK) {
+        for (const dart_tuning &c : cands) {
+            float ms = 0;
+            result = measure(c, &ms);
+            if (result != DART_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
         }
     }
     for (int32_t i = 0; i < n; i++) {

@@ -87,10 +87,13 @@ struct Req {
     void *dest = nullptr;
     bool host_dest = false;
     size_t img_bytes = 0;
+    size_t desc_bound = 0;  // upper bound of the request's share of a wave's descriptors
     size_t dev_off = 0, host_off = 0;
     bool admitted = false;
+    bool waited = false;  // counted once in admission_waits
     Clock::time_point t_submit;
     double latency_ms = 0, flux = 0;
+    uint64_t steps = 0;
     int state = 0;  // 0 queued, 1 admitted, 2 running, 3 done, 4 failed
     dart_status err = DART_OK;
     std::string err_msg;
@@ -99,8 +102,6 @@ struct Req {
 struct Wave {
     std::vector<Req *> reqs;
     int stream_idx = 0;
-    size_t desc_off = 0, desc_bytes = 0;
-    size_t stage_off = 0, stage_bytes = 0;
     bool done = false;
     Clock::time_point t_done;
     struct dart_server *srv = nullptr;
@@ -114,6 +115,10 @@ struct dart_server {
     int max_inflight = 0;
     std::vector<hipStream_t> streams;
     std::vector<bool> stream_busy;
+    // per stream: descriptor buffer on the device and its pinned upload staging
+    // (also the flux / step readback), fixed at creation and outside the budget
+    std::vector<void *> desc_dev, desc_host;
+    size_t desc_cap = 0;
     void *dev_base = nullptr;    // device arena: images and wave descriptors
     void *host_base = nullptr;   // pinned arena: descriptor uploads, flux readback, host images
     size_t host_size = 0;
@@ -142,13 +147,13 @@ static void on_wave_done(void *p) {
 // Frees a finished wave's resources and publishes its results.  Caller holds mu.
 static void retire(dart_server *srv, Wave *w) {
     const size_t n = w->reqs.size();
-    const unsigned long long *acc_h =
-        (const unsigned long long *)((char *)srv->host_base + w->stage_off);
+    const unsigned long long *acc_h = (const unsigned long long *)srv->desc_host[w->stream_idx];
     for (size_t i = 0; i < n; i++) {
         Req *r = w->reqs[i];
         double f;
         memcpy(&f, &acc_h[i], sizeof(f));
         r->flux = f;
+        r->steps = acc_h[n + i];
         if (r->host_dest)
             memcpy(r->dest, (char *)srv->host_base + r->host_off, r->img_bytes);
         r->latency_ms =
@@ -160,8 +165,6 @@ static void retire(dart_server *srv, Wave *w) {
         srv->admitted--;
         srv->stats.completed++;
     }
-    srv->dev_arena.release(w->desc_off, w->desc_bytes);
-    srv->host_arena.release(w->stage_off, w->stage_bytes);
     srv->stream_busy[w->stream_idx] = false;
     srv->stats.bytes_in_use = srv->dev_arena.used();
 }
@@ -176,27 +179,31 @@ static void fail_wave(dart_server *srv, Wave *w, dart_status st, const std::stri
         const_cast<dart_stack *>(r->stack)->pinned--;
         srv->admitted--;
     }
-    if (w->desc_bytes) srv->dev_arena.release(w->desc_off, w->desc_bytes);
-    if (w->stage_bytes) srv->host_arena.release(w->stage_off, w->stage_bytes);
     srv->stream_busy[w->stream_idx] = false;
 }
 
 // Admission: FIFO, stop at the first request that does not fit.  Caller holds mu.
 static void admit(dart_server *srv) {
+    auto wait = [srv](Req *r) {
+        if (!r->waited) {
+            r->waited = true;
+            srv->stats.admission_waits++;
+        }
+    };
     for (Req *r : srv->queue) {
         if (r->admitted) continue;
         if (srv->admitted >= srv->max_inflight) {
-            srv->stats.admission_waits++;
+            wait(r);
             return;
         }
         size_t doff = 0, hoff = 0;
         if (!srv->dev_arena.alloc(r->img_bytes, &doff)) {
-            srv->stats.admission_waits++;
+            wait(r);
             return;
         }
         if (r->host_dest && !srv->host_arena.alloc(r->img_bytes, &hoff)) {
             srv->dev_arena.release(doff, r->img_bytes);
-            srv->stats.admission_waits++;
+            wait(r);
             return;
         }
         r->dev_off = doff;
@@ -217,7 +224,12 @@ static void launch_wave(dart_server *srv, std::unique_lock<std::mutex> &lk, int 
     std::unique_ptr<Wave> w(new Wave());
     w->srv = srv;
     w->stream_idx = sidx;
-    while (!srv->queue.empty() && srv->queue.front()->admitted) {
+    // 256-B alignment of the accumulators + 64 B per request (flux, steps and
+    // queue heads) on top of each request's descriptor bound
+    size_t bound = 320;
+    while (!srv->queue.empty() && srv->queue.front()->admitted &&
+           (w->reqs.empty() || bound + srv->queue.front()->desc_bound <= srv->desc_cap)) {
+        bound += srv->queue.front()->desc_bound;
         w->reqs.push_back(srv->queue.front());
         srv->queue.pop_front();
     }
@@ -245,24 +257,10 @@ static void launch_wave(dart_server *srv, std::unique_lock<std::mutex> &lk, int 
     assign_offsets(groups, &nv, &nt);
     const size_t acc_u64 = 2 * (size_t)n + 4 * groups.size();
     const size_t desc_bytes = nv * sizeof(RayView) + nt * sizeof(Tile);
-    w->desc_bytes = ((desc_bytes + 255) & ~(size_t)255) + acc_u64 * 8;
-    w->stage_bytes = std::max(desc_bytes, acc_u64 * 8);
-    const bool got_dev = srv->dev_arena.alloc(w->desc_bytes, &w->desc_off);
-    const bool got_host = got_dev && srv->host_arena.alloc(w->stage_bytes, &w->stage_off);
-    if (!got_host) {
-        if (got_dev) srv->dev_arena.release(w->desc_off, w->desc_bytes);
-        w->desc_bytes = 0;
-        w->stage_bytes = 0;
-        if (srv->waves.empty()) {
-            // nothing in flight will free memory: the wave can never start
-            fail_wave(srv, w.get(), DART_E_NOMEM, "wave descriptors exceed the server budget");
-            return;
-        }
-        // put the requests back and retry when a running wave frees memory
-        for (int32_t i = n - 1; i >= 0; i--) {
-            w->reqs[i]->state = 1;
-            srv->queue.push_front(w->reqs[i]);
-        }
+    const size_t acc_off = (desc_bytes + 255) & ~(size_t)255;
+    if (acc_off + acc_u64 * 8 > srv->desc_cap) {
+        // cannot happen: the per-request bounds cover the plan
+        fail_wave(srv, w.get(), DART_E_INTERNAL, "wave descriptors exceed their buffer");
         return;
     }
     srv->stream_busy[sidx] = true;
@@ -270,10 +268,9 @@ static void launch_wave(dart_server *srv, std::unique_lock<std::mutex> &lk, int 
     if ((uint64_t)n > srv->stats.max_wave_requests) srv->stats.max_wave_requests = n;
     Wave *wp = w.get();
     srv->waves.push_back(std::move(w));
-    char *hstage = (char *)srv->host_base + wp->stage_off;
-    char *ddesc = (char *)srv->dev_base + wp->desc_off;
-    unsigned long long *dacc =
-        (unsigned long long *)(ddesc + ((desc_bytes + 255) & ~(size_t)255));
+    char *hstage = (char *)srv->desc_host[sidx];
+    char *ddesc = (char *)srv->desc_dev[sidx];
+    unsigned long long *dacc = (unsigned long long *)(ddesc + acc_off);
     pack_descriptors(groups, nv, hstage);
     hipStream_t stream = srv->streams[sidx];
     lk.unlock();
@@ -289,9 +286,9 @@ static void launch_wave(dart_server *srv, std::unique_lock<std::mutex> &lk, int 
         else
             e = hipMemcpyAsync(r->dest, imgs[i], r->img_bytes, hipMemcpyDeviceToDevice, stream);
     }
-    // the flux accumulators overwrite the (already consumed) descriptor staging
+    // the flux and step accumulators overwrite the (already consumed) descriptor staging
     if (e == hipSuccess)
-        e = hipMemcpyAsync(hstage, dacc, (size_t)n * 8, hipMemcpyDeviceToHost, stream);
+        e = hipMemcpyAsync(hstage, dacc, (size_t)n * 16, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) {
         for (int32_t i = 0; i < n; i++) note_use(stacks[i], stream);
         e = hipLaunchHostFunc(stream, on_wave_done, wp);
@@ -376,6 +373,24 @@ extern "C" dart_status dart_server_create(size_t hbm_budget_bytes, int32_t max_i
         srv->streams.push_back(s);
         srv->stream_busy.push_back(false);
     }
+    // room for at least one 1024^2 request of 1x64 tiles, up to 64 MiB per stream
+    srv->desc_cap = std::max((size_t)4 << 20, std::min((size_t)64 << 20, hbm_budget_bytes / 4));
+    for (int32_t k = 0; k < n_streams; k++) {
+        void *d = nullptr, *h = nullptr;
+        e = hipMalloc(&d, srv->desc_cap);
+        if (e == hipSuccess) e = hipHostMalloc(&h, srv->desc_cap, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            if (d) (void)hipFree(d);
+            for (void *q : srv->desc_dev) (void)hipFree(q);
+            for (void *q : srv->desc_host) (void)hipHostFree(q);
+            for (hipStream_t q : srv->streams) (void)hipStreamDestroy(q);
+            (void)hipFree(srv->dev_base);
+            (void)hipHostFree(srv->host_base);
+            return hip_fail(e, "server descriptor buffers");
+        }
+        srv->desc_dev.push_back(d);
+        srv->desc_host.push_back(h);
+    }
     dart_server *p = srv.get();
     srv->thr = std::thread(scheduler, p);
     *out = srv.release();
@@ -395,6 +410,13 @@ extern "C" dart_status dart_submit(dart_server *srv, const dart_stack *s, const 
     r->dest = image;
     r->host_dest = !(v->flags & DART_DEVICE_PTRS);
     r->img_bytes = (size_t)v->width * v->height * 4;
+    // any 64-pixel tile shape w x h cuts the image into at most
+    // (W/w + 1)(H/h + 1) <= WH/64 + W + H + 1 tiles
+    r->desc_bound = sizeof(RayView) + 64 +
+                    ((size_t)v->width * v->height / 64 + v->width + v->height + 1) * sizeof(Tile);
+    if (r->desc_bound + 256 > srv->desc_cap)
+        return fail(DART_E_NOMEM, "a %dx%d image needs more wave descriptors than the server holds",
+                    v->width, v->height);
     if (r->img_bytes + (1u << 20) > srv->budget ||
         (r->host_dest && r->img_bytes + (1u << 20) > srv->host_size))
         return fail(DART_E_NOMEM, "a %dx%d image cannot fit the server budget", v->width,
@@ -411,12 +433,13 @@ extern "C" dart_status dart_submit(dart_server *srv, const dart_stack *s, const 
     return DART_OK;
 }
 
-static dart_status collect(dart_server *srv, Req *r, double *flux, double *latency_ms,
-                           uint64_t ticket) {
+static dart_status collect(dart_server *srv, Req *r, double *flux, uint64_t *steps,
+                           double *latency_ms, uint64_t ticket) {
     dart_status st = r->state == 4 ? r->err : DART_OK;
     std::string msg = r->err_msg;
     if (st == DART_OK) {
         if (flux) *flux = r->flux;
+        if (steps) *steps = r->steps;
         if (latency_ms) *latency_ms = r->latency_ms;
     }
     srv->reqs.erase(ticket);
@@ -425,7 +448,7 @@ static dart_status collect(dart_server *srv, Req *r, double *flux, double *laten
 }
 
 extern "C" dart_status dart_poll(dart_server *srv, uint64_t ticket, int32_t *done, double *flux,
-                                 double *latency_ms) {
+                                 uint64_t *steps, double *latency_ms) {
     if (!srv || !done) return fail(DART_E_INVAL, "NULL argument");
     std::lock_guard<std::mutex> g(srv->mu);
     auto it = srv->reqs.find(ticket);
@@ -436,10 +459,10 @@ extern "C" dart_status dart_poll(dart_server *srv, uint64_t ticket, int32_t *don
         return DART_OK;
     }
     *done = 1;
-    return collect(srv, r, flux, latency_ms, ticket);
+    return collect(srv, r, flux, steps, latency_ms, ticket);
 }
 
-extern "C" dart_status dart_wait(dart_server *srv, uint64_t ticket, double *flux,
+extern "C" dart_status dart_wait(dart_server *srv, uint64_t ticket, double *flux, uint64_t *steps,
                                  double *latency_ms) {
     if (!srv) return fail(DART_E_INVAL, "NULL server");
     std::unique_lock<std::mutex> lk(srv->mu);
@@ -447,7 +470,7 @@ extern "C" dart_status dart_wait(dart_server *srv, uint64_t ticket, double *flux
     if (it == srv->reqs.end()) return fail(DART_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
     Req *r = it->second.get();
     srv->cv.wait(lk, [r] { return r->state >= 3; });
-    return collect(srv, r, flux, latency_ms, ticket);
+    return collect(srv, r, flux, steps, latency_ms, ticket);
 }
 
 extern "C" dart_status dart_server_get_stats(dart_server *srv, dart_server_stats *st) {
@@ -470,6 +493,8 @@ extern "C" dart_status dart_server_destroy(dart_server *srv) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
     }
+    for (void *q : srv->desc_dev) (void)hipFree(q);
+    for (void *q : srv->desc_host) (void)hipHostFree(q);
     (void)hipFree(srv->dev_base);
     (void)hipHostFree(srv->host_base);
     delete srv;

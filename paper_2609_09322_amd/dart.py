@@ -116,8 +116,8 @@ def _load():
         "dart_bandwidth_probe": [_P, _P, U64, I32, _P],
         "dart_server_create": [ctypes.c_size_t, I32, I32, _P],
         "dart_submit": [_P, _P, _P, _P, _P],
-        "dart_poll": [_P, U64, _P, _P, _P],
-        "dart_wait": [_P, U64, _P, _P],
+        "dart_poll": [_P, U64, _P, _P, _P, _P],
+        "dart_wait": [_P, U64, _P, _P, _P],
         "dart_server_destroy": [_P],
         "dart_server_get_stats": [_P, _P],
     }
@@ -347,19 +347,24 @@ def dart_submit(srv: Server, stack: Stack, view: View, image) -> int:
 
 
 def dart_poll(srv: Server, ticket):
+    """(done, flux, cell_steps, latency_ms); a done ticket is retired."""
     done = ctypes.c_int32(0)
     f = ctypes.c_double(0)
+    n = ctypes.c_uint64(0)
     lat = ctypes.c_double(0)
     _check(_load().dart_poll(srv.handle, int(ticket), ctypes.byref(done), ctypes.byref(f),
-                             ctypes.byref(lat)))
-    return bool(done.value), f.value, lat.value
+                             ctypes.byref(n), ctypes.byref(lat)))
+    return bool(done.value), f.value, n.value, lat.value
 
 
 def dart_wait(srv: Server, ticket):
+    """Blocks until the request is done: (flux, cell_steps, latency_ms)."""
     f = ctypes.c_double(0)
+    n = ctypes.c_uint64(0)
     lat = ctypes.c_double(0)
-    _check(_load().dart_wait(srv.handle, int(ticket), ctypes.byref(f), ctypes.byref(lat)))
-    return f.value, lat.value
+    _check(_load().dart_wait(srv.handle, int(ticket), ctypes.byref(f), ctypes.byref(n),
+                             ctypes.byref(lat)))
+    return f.value, n.value, lat.value
 
 
 def dart_server_get_stats(srv: Server) -> dart_server_stats:

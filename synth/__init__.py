@@ -262,3 +262,13 @@ def round_bf16(x):
     lsb = (u >> 16) & 1
     r = ((u + 0x7FFF + lsb) >> 16) << 16
     return r.astype(np.uint32).view(np.float32)
+
+
+def to_bf16_bits(x):
+    """bfloat16 bit patterns (uint16) of float32 values, rounded to nearest even."""
+    return (round_bf16(x).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def to_f16(x):
+    """IEEE binary16 values of float32 inputs (numpy rounds to nearest even)."""
+    return np.asarray(x, dtype=np.float32).astype(np.float16)

@@ -546,3 +546,52 @@ def test_count_samples_small(orc):
                     if w > 0:
                         seen.add((m, int(c)))
     assert orc.count_samples(s, v) == len(seen)
+
+
+# ---------------------------------------------------------------- 16-bit inputs, streaming
+
+def test_sixteen_bit_inputs_decode_exactly(orc):
+    """binary16 and bfloat16 arrays are widened by the oracle's own decoder:
+    the render equals the render of the same values widened by numpy."""
+    n = 8
+    j, beta, t = synth.random_stack((n, n, n), 4, seed=71, beta_max=0.9, dtype=np.float32)
+    v = orc.View(40.0, 70.0, 14, 12, 1.1, float(t.mean()), 0.6, 0)
+    h_j, h_b = synth.to_f16(j), synth.to_f16(beta)
+    a, _ = orc.render(orc.Stack(h_j, h_b, t), v, threads=1)
+    b, _ = orc.render(orc.Stack(h_j.astype(np.float64), h_b.astype(np.float64), t), v, threads=1)
+    np.testing.assert_array_equal(a, b)
+    r_j, r_b = synth.to_bf16_bits(j), synth.to_bf16_bits(beta)
+    a, _ = orc.render(orc.Stack(r_j, r_b, t, encoding="bf16"), v, threads=1)
+    b, _ = orc.render(orc.Stack(synth.round_bf16(j).astype(np.float64),
+                                synth.round_bf16(beta).astype(np.float64), t), v, threads=1)
+    np.testing.assert_array_equal(a, b)
+    # binary16 specials: subnormals, the largest finite value, signed zero
+    bits = np.array([0x0001, 0x03FF, 0x7BFF, 0x8000, 0x3C00, 0xC000], dtype=np.uint16)
+    vals = bits.view(np.float16).astype(np.float64)
+    jj = np.zeros((1, 1, 1, len(bits)), dtype=np.float16)
+    jj[0, 0, 0, :] = bits.view(np.float16)
+    s16 = orc.Stack(jj, np.zeros((1, 1, 1, len(bits), 3), dtype=np.float16), [0.0])
+    # s_hat = -z and (phi = 90) e_u = -x: pixel i sees the column of cell x = n - 1 - i
+    img, _ = orc.render(s16, orc.View(0.0, 90.0, len(bits), 1, 1.0, 0.0, 0.0,
+                                      orc.NO_LOOKBACK | orc.NO_BEAMING), threads=1)
+    np.testing.assert_array_equal(img[0, ::-1], vals)
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+def test_streamed_equals_whole(orc, flags):
+    """The snapshot-outer form (one epoch interval at a time, two epochs held)
+    sums the same cells as the whole render."""
+    dims = (9, 7, 11)
+    j, beta, t = synth.random_stack(dims, 7, seed=81, beta_max=0.9)
+    s = orc.Stack(j, beta, t)
+    for th, ph in [(35.0, 20.0), (90.0, 0.0), (150.0, 260.0)]:
+        v = orc.View(th, ph, 16, 14, 0.9, float(t[0] + 0.55 * (t[-1] - t[0])), 0.6, flags)
+        whole, n_whole = orc.render(s, v, threads=2)
+        streamed, n_str = orc.render_streamed(t, lambda m: (j[m:m + 2], beta[m:m + 2]), v, threads=2)
+        np.testing.assert_allclose(streamed, whole, rtol=1e-13, atol=1e-14 * np.abs(whole).max())
+        assert n_str == n_whole
+    # no lookback: the single interval that holds t_obs
+    v = orc.View(50.0, 30.0, 12, 12, 1.0, float(t[3] + 0.3 * (t[4] - t[3])), 0.6, orc.NO_LOOKBACK)
+    whole, _ = orc.render(s, v, threads=1)
+    streamed, _ = orc.render_streamed(t, lambda m: (j[m:m + 2], beta[m:m + 2]), v, threads=1)
+    np.testing.assert_allclose(streamed, whole, rtol=1e-13)
