@@ -222,9 +222,10 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
     cpu = None
     if not args.no_cpu_baseline and host is not None:
         threads = os.cpu_count() or 1
-        # calibrate on a small sample, then size the sample for ~10-20 s
-        _, n0, s0 = oracle_sample(host, times, views, 64 * n_img, 11, threads, dtype_name)
-        rays = int(min(1 << 22, max(64 * n_img, 64 * n_img * 12.0 / max(s0, 1e-3))))
+        # calibrate on a sample of ~1 s, then size the timed sample for ~15 s
+        cal = 8192 * max(1, 16 // n_img) * n_img
+        _, n0, s0 = oracle_sample(host, times, views, cal, 11, threads, dtype_name)
+        rays = int(min(1 << 23, max(cal, cal * 15.0 / max(s0, 1e-3))))
         _, n1, s1 = oracle_sample(host, times, views, rays, 12, threads, dtype_name)
         cpu = {"value": n1 / s1, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{rays} random pixels over the {n_img} views ({n1} cell-steps, {s1:.1f} s)",
