@@ -94,7 +94,7 @@ def _load():
                                          ctypes.c_int, ctypes.c_int]
         lib.orc_render_window.restype = ctypes.c_int
         lib.orc_render_window.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_View), ctypes.c_int,
-                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
                                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),
                                           ctypes.c_int]
@@ -105,7 +105,7 @@ def _load():
     return _lib
 
 
-_DT_CODE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+_DT_CODE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32_as_bf16": 4, "f32_as_f16": 5}
 
 
 @dataclass
@@ -113,7 +113,9 @@ class Stack:
     """Epoch stack in the caller's layout: j [M][nz][ny][nx], beta [M][nz][ny][nx][3].
 
     Arrays may be float64, float32, float16, or uint16 holding bfloat16 bit
-    patterns (encoding="bf16"); the oracle widens every value to FP64 itself."""
+    patterns (encoding="bf16"); float32 arrays with encoding "f32_as_bf16" or
+    "f32_as_f16" are rounded to that 16-bit type value by value as they are
+    read.  The oracle widens every value to FP64 itself."""
     j: np.ndarray
     beta: np.ndarray
     times: np.ndarray
@@ -124,7 +126,8 @@ class Stack:
         if self.encoding is None:
             self.encoding = {np.dtype(np.float32): "f32", np.dtype(np.float16): "f16",
                              np.dtype(np.uint16): "bf16"}.get(np.dtype(self.j.dtype), "f64")
-        dt = {"f64": np.float64, "f32": np.float32, "f16": np.float16, "bf16": np.uint16}[self.encoding]
+        dt = {"f64": np.float64, "f32": np.float32, "f16": np.float16, "bf16": np.uint16,
+              "f32_as_bf16": np.float32, "f32_as_f16": np.float32}[self.encoding]
         self.j = np.ascontiguousarray(self.j, dtype=dt)
         self.beta = np.ascontiguousarray(self.beta, dtype=dt)
         self.times = np.ascontiguousarray(self.times, dtype=np.float64)
@@ -204,10 +207,11 @@ def render_brute(stack: Stack, view: View, pixels=None, threads=None):
 
 
 def render_window(times, j_sub, beta_sub, e0, view: View, t_lo, t_hi, hi_closed, out,
-                  pixels=None, cell=(1.0, 1.0, 1.0), encoding=None, threads=None):
+                  pixels=None, cell=(1.0, 1.0, 1.0), encoding=None, threads=None, ring=False):
     """Snapshot-outer O1: ``j_sub``/``beta_sub`` hold epochs [e0, e0 + n) of a
-    stack whose epoch times are ``times`` (all M); ADDS to ``out`` the cells
-    whose retarded time lies in [t_lo, t_hi) ([t_lo, t_hi] if hi_closed).
+    stack whose epoch times are ``times`` (all M), in order, or (ring=True) as
+    a ring with epoch e in slot e mod n; ADDS to ``out`` the cells whose
+    retarded time lies in [t_lo, t_hi) ([t_lo, t_hi] if hi_closed).
     Returns the cell-steps of the interval."""
     lib = _load()
     sub = Stack(j_sub, beta_sub, np.zeros(j_sub.shape[0]), cell=cell, encoding=encoding)
@@ -224,7 +228,8 @@ def render_window(times, j_sub, beta_sub, e0, view: View, t_lo, t_hi, hi_closed,
         pix_ptr, n = pix.ctypes.data, pix.shape[0]
     steps = ctypes.c_longlong(0)
     rc = lib.orc_render_window(ctypes.byref(g), ctypes.byref(view._cview()), int(e0),
-                               int(j_sub.shape[0]), float(t_lo), float(t_hi), int(hi_closed),
+                               int(j_sub.shape[0]), int(bool(ring)), float(t_lo), float(t_hi),
+                               int(hi_closed),
                                pix_ptr, n, out.ctypes.data, ctypes.byref(steps), _threads(threads))
     if rc != 0:
         raise ValueError(f"oracle window render failed (rc={rc})")
@@ -232,10 +237,11 @@ def render_window(times, j_sub, beta_sub, e0, view: View, t_lo, t_hi, hi_closed,
 
 
 def render_streamed(times, epoch_loader, view: View, pixels=None, cell=(1.0, 1.0, 1.0),
-                    encoding=None, threads=None):
+                    encoding=None, threads=None, ring=False):
     """Whole image (or pixel list) by the snapshot-outer form: for every
     interval [t_m, t_{m+1}) the caller's ``epoch_loader(m)`` returns
-    (j_sub, beta_sub) for epochs m and m+1.  Two epochs are held at a time."""
+    (j_sub, beta_sub) holding epochs m and m+1 (in order, or with ring=True as
+    a two-slot ring, epoch e in slot e mod 2).  Two epochs are held at a time."""
     t = np.asarray(times, dtype=np.float64)
     M = len(t)
     if pixels is None:
@@ -249,16 +255,18 @@ def render_streamed(times, epoch_loader, view: View, pixels=None, cell=(1.0, 1.0
             return out, 0
         m = 0 if M == 1 else min(int(np.searchsorted(t, view.t_obs, side="right")) - 1, M - 2)
         js, bs = epoch_loader(m)
-        steps += render_window(t, js, bs, m, view, -np.inf, np.inf, 1, out, pixels, cell, encoding, threads)
+        steps += render_window(t, js, bs, m, view, -np.inf, np.inf, 1, out, pixels, cell, encoding,
+                               threads, ring)
         return out, steps
     if M == 1:
         js, bs = epoch_loader(0)
-        steps += render_window(t, js, bs, 0, view, t[0], t[0], 1, out, pixels, cell, encoding, threads)
+        steps += render_window(t, js, bs, 0, view, t[0], t[0], 1, out, pixels, cell, encoding,
+                               threads, ring)
         return out, steps
     for m in range(M - 1):
         js, bs = epoch_loader(m)
         steps += render_window(t, js, bs, m, view, t[m], t[m + 1], int(m == M - 2), out, pixels,
-                               cell, encoding, threads)
+                               cell, encoding, threads, ring)
     return out, steps
 
 

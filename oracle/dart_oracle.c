@@ -50,6 +50,8 @@
 #define ORC_DT_F32 1
 #define ORC_DT_F16 2  /* IEEE binary16 bit patterns (uint16) */
 #define ORC_DT_BF16 3 /* bfloat16 bit patterns (uint16): the top half of a binary32 */
+#define ORC_DT_F32_AS_BF16 4 /* float32 arrays, each value rounded to bfloat16 when read */
+#define ORC_DT_F32_AS_F16 5  /* float32 arrays, each value rounded to binary16 when read */
 
 typedef struct {
     int n[3];             /* cells along x, y, z */
@@ -95,8 +97,38 @@ static double half_to_double(uint16_t h) {
     return sign ? -v : v;
 }
 
+/* Round-to-nearest-even of a finite binary32 to the nearest bfloat16, done on
+ * the integer representation: add half an ulp of the 16 kept bits (rounding
+ * ties toward the even kept pattern) and drop the low 16 bits. */
+static double f32_round_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, sizeof(u));
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    memcpy(&f, &u, sizeof(f));
+    return (double)f;
+}
+
+/* Round-to-nearest-even of a binary32 to binary16 (finite, normal range and
+ * subnormals), returned widened: the value is scaled so that the binary16
+ * ulp at its exponent becomes 1, rounded to an integer with ties to even by
+ * nearbyint (default rounding mode), and scaled back. */
+static double f32_round_f16(float f) {
+    double x = (double)f, a = fabs(x);
+    if (a == 0.0) return x;
+    int e;
+    frexp(a, &e);                 /* a = m 2^e, m in [0.5, 1) */
+    int ulp_exp = (e - 1) - 10;   /* 10 fraction bits */
+    if (ulp_exp < -24) ulp_exp = -24; /* subnormal spacing 2^-24 */
+    double q = nearbyint(ldexp(x, -ulp_exp));
+    double r = ldexp(q, ulp_exp);
+    if (fabs(r) > 65504.0) return x > 0 ? INFINITY : -INFINITY;
+    return r;
+}
+
 static double load_val(const void *p, int dtype, size_t idx) {
     if (dtype == ORC_DT_F32) return (double)((const float *)p)[idx];
+    if (dtype == ORC_DT_F32_AS_BF16) return f32_round_bf16(((const float *)p)[idx]);
+    if (dtype == ORC_DT_F32_AS_F16) return f32_round_f16(((const float *)p)[idx]);
     if (dtype == ORC_DT_F16) return half_to_double(((const uint16_t *)p)[idx]);
     if (dtype == ORC_DT_BF16) {
         uint32_t u = (uint32_t)((const uint16_t *)p)[idx] << 16;
@@ -199,6 +231,7 @@ typedef struct {
     int e0, ne;
     double t_lo, t_hi;
     int hi_closed;
+    int ring; /* 0: epoch e is at slot e - e0; 1: at slot e mod ne (a ring of ne epochs) */
 } orc_window;
 
 static __thread const orc_window *tl_win = NULL;
@@ -226,8 +259,8 @@ static int cell_term(const orc_grid *g, const orc_view *v, const double shat[3],
         if (ws[q] == 0.0) continue;
         int me = ms[q];
         if (w && w->ne > 0) {
-            me -= w->e0;
-            if (me < 0 || me >= w->ne) return -1; /* the caller did not load this epoch */
+            if (me < w->e0 || me >= w->e0 + w->ne) return -1; /* the caller did not load it */
+            me = w->ring ? me % w->ne : me - w->e0;
         }
         size_t r = (size_t)me * ncell + c;
         double jv = load_val(g->j, g->dtype, r);
@@ -427,15 +460,16 @@ int orc_render(const orc_grid *g, const orc_view *v, const int32_t *pix, long lo
 /* Snapshot-outer form of O1 (the chronology of the paper's Fig. 5): the grid's
  * arrays hold only epochs [e0, e0 + ne) (times still lists all M epochs), and
  * the call ADDS to out[] the contributions of the cells whose retarded time
- * lies in [t_lo, t_hi) (or [t_lo, t_hi] with hi_closed).  Summing the calls
+ * lies in [t_lo, t_hi) (or [t_lo, t_hi] with hi_closed).  With ring != 0 the
+ * arrays are a ring of ne slots and epoch e sits in slot e mod ne.  Summing the calls
  * over the intervals [t_m, t_{m+1}) with epochs {m, m+1} loaded, the last one
  * closed, gives the whole image while only two epochs are held at a time.
  * Returns -2 when a cell in the interval needs an epoch that was not loaded. */
-int orc_render_window(const orc_grid *g, const orc_view *v, int e0, int ne, double t_lo,
+int orc_render_window(const orc_grid *g, const orc_view *v, int e0, int ne, int ring, double t_lo,
                       double t_hi, int hi_closed, const int32_t *pix, long long n_pix, double *out,
                       long long *steps_out, int nthreads) {
     if (ne < 1 || e0 < 0 || e0 + ne > g->n_epochs) return -1;
-    orc_window w = {e0, ne, t_lo, t_hi, hi_closed};
+    orc_window w = {e0, ne, t_lo, t_hi, hi_closed, ring};
     return run_ex(g, v, pix, n_pix, out, steps_out, nthreads, 0, &w, 1);
 }
 

@@ -590,8 +590,53 @@ def test_streamed_equals_whole(orc, flags):
         streamed, n_str = orc.render_streamed(t, lambda m: (j[m:m + 2], beta[m:m + 2]), v, threads=2)
         np.testing.assert_allclose(streamed, whole, rtol=1e-13, atol=1e-14 * np.abs(whole).max())
         assert n_str == n_whole
+        # the same through a two-slot ring (epoch e in slot e mod 2)
+        jr, br = np.zeros_like(j[:2]), np.zeros_like(beta[:2])
+
+        def ring_loader(m):
+            for e in (m, m + 1):
+                jr[e % 2], br[e % 2] = j[e], beta[e]
+            return jr, br
+        ringed, n_ring = orc.render_streamed(t, ring_loader, v, threads=2, ring=True)
+        np.testing.assert_array_equal(ringed, streamed)
+        assert n_ring == n_whole
     # no lookback: the single interval that holds t_obs
     v = orc.View(50.0, 30.0, 12, 12, 1.0, float(t[3] + 0.3 * (t[4] - t[3])), 0.6, orc.NO_LOOKBACK)
     whole, _ = orc.render(s, v, threads=1)
     streamed, _ = orc.render_streamed(t, lambda m: (j[m:m + 2], beta[m:m + 2]), v, threads=1)
     np.testing.assert_allclose(streamed, whole, rtol=1e-13)
+
+
+def test_round_on_read_matches_numpy_rounding(orc):
+    """f32_as_bf16 / f32_as_f16 round each float32 while reading; the renders
+    equal the renders of arrays rounded by numpy (f16) or by bit arithmetic
+    in numpy (bf16), including ties, subnormals and overflow-free large values."""
+    n = 8
+    rng = np.random.default_rng(91)
+    j = rng.uniform(0, 3, size=(3, n, n, n)).astype(np.float32)
+    j.reshape(-1)[:6] = np.array([1.0009765625, 1.00048828125, 3.0517578125e-05, 2.9802322e-08,
+                                  6.1035156e-05, 65000.0], dtype=np.float32)
+    beta = (rng.uniform(-0.55, 0.55, size=(3, n, n, n, 3))).astype(np.float32)
+    t = np.array([0.0, 4.0, 9.0])
+    v = orc.View(33.0, 12.0, 12, 12, 1.2, 4.5, 0.7, 0)
+    for enc, ref_j, ref_b in [("f32_as_bf16", synth.round_bf16(j), synth.round_bf16(beta)),
+                              ("f32_as_f16", synth.round_f16(j), synth.round_f16(beta))]:
+        a, _ = orc.render(orc.Stack(j, beta, t, encoding=enc), v, threads=1)
+        b, _ = orc.render(orc.Stack(ref_j.astype(np.float64), ref_b.astype(np.float64), t), v, threads=1)
+        np.testing.assert_array_equal(a, b)
+
+
+def test_round_on_read_special_values(orc):
+    """Ties to even, subnormal binary16 spacing and the largest binary16 value,
+    one value per cell of a one-row grid read back through a cardinal view."""
+    vals = np.array([1.0009765625, 1.00048828125, 1.0029296875, 3.0517578125e-05,
+                     2.9802322e-08, 5.9604645e-08, 65504.0, 1.00390625, 1.005859375,
+                     -2.7182817, 0.0], dtype=np.float32)
+    k = len(vals)
+    jj = vals.reshape(1, 1, 1, k)
+    bb = np.zeros((1, 1, 1, k, 3), dtype=np.float32)
+    view = orc.View(0.0, 90.0, k, 1, 1.0, 0.0, 0.0, orc.NO_LOOKBACK | orc.NO_BEAMING)
+    for enc, ref in [("f32_as_f16", vals.astype(np.float16).astype(np.float64)),
+                     ("f32_as_bf16", synth.round_bf16(vals).astype(np.float64))]:
+        img, _ = orc.render(orc.Stack(jj, bb, [0.0], encoding=enc), view, threads=1)
+        np.testing.assert_array_equal(img[0, ::-1], ref)
