@@ -271,16 +271,24 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
 
 
 def build_stack_incremental(dart, torch, dims, n_epochs, seed, gamma, knots, storage,
-                            chunk_bytes=8 << 30):
+                            chunk_bytes=8 << 30, z_slab=None):
     """Creates a stack and fills it a few epochs at a time from device-generated
-    float32 fields (the two-phase load for stacks too large to stage whole)."""
+    float32 fields (the two-phase load for stacks too large to stage whole).
+    z_slab=(z0, nz_slab) makes a stack of those z-layers of the domain `dims`,
+    placed in the domain so that its renders are partial renders of the whole."""
     import synth
     times = synth.jet_times(dims, n_epochs)
-    st = dart.dart_stack_create(dims, (1.0, 1.0, 1.0), times, storage)
     nx, ny, nz = dims
+    params = synth.jet_params(dims, seed, gamma_spine=gamma, n_knots=knots)
+    if z_slab is not None:
+        params.z_begin, params.z_count = int(z_slab[0]), int(z_slab[1])
+    st = dart.dart_stack_create((nx, ny, params.z_count), (1.0, 1.0, 1.0), times, storage)
+    if z_slab is not None:
+        dart.dart_stack_set_placement(st, (0.0, 0.0, float(params.z_begin)),
+                                      (0.5 * nx, 0.5 * ny, 0.5 * nz))
+    nz = params.z_count
     per_epoch = nx * ny * nz * 16
     chunk = max(1, min(n_epochs, chunk_bytes // per_epoch))
-    params = synth.jet_params(dims, seed, gamma_spine=gamma, n_knots=knots)
     stream = torch.cuda.current_stream()
     jbuf = torch.empty((chunk, nz, ny, nx), dtype=torch.float32, device="cuda")
     bbuf = torch.empty((chunk, nz, ny, nx, 3), dtype=torch.float32, device="cuda")
@@ -502,6 +510,13 @@ def run_large_workload(args, dart, torch):
                "tolerance": {"flux": 1e-6, "pixel": 2e-3}}
         log(f"oracle check: {acc}")
     achieved = est_compulsory / (float(np.mean(per)) * 1e-3) / 1e9
+    slabs = None
+    if args.large_slabs > 1:
+        torch.cuda.synchronize()
+        dart.dart_free_epochs(st)
+        slabs = render_slabs(args, dart, torch, dims, M, seed, gamma, knots, views, imgs, flux,
+                             steps, stream)
+        log(f"slabs: {slabs}")
     return {
         "metric": "cell-steps/s & images/s (batched vs plain kernel) at 1e-5 rel; p50/p99 ms",
         "value": cell_steps / (ms_step * 1e-3), "unit": "cell-steps/s", "n_gpus": 1,
@@ -517,8 +532,58 @@ def run_large_workload(args, dart, torch):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_definition": "compulsory records estimated from 4 counted views"},
-        "accuracy": acc, "tuning": tuning, "cpu_baseline": None,
+        "accuracy": acc, "tuning": tuning, "cpu_baseline": None, "slabs": slabs,
     }
+
+
+def render_slabs(args, dart, torch, dims, M, seed, gamma, knots, views, whole_imgs, whole_flux,
+                 whole_steps, stream):
+    """Domain slabs on one GPU: the grid is cut into z-slabs; each is loaded
+    alone (the share one GPU of a slab-sharded job would hold), placed in the
+    domain, and rendered with every view adding into one set of images.  The
+    sum must equal the render of the whole domain (flux within 1e-6)."""
+    nx, ny, nz = dims
+    k = args.large_slabs
+    cuts = [round(i * nz / k) for i in range(k + 1)]
+    n = len(views)
+    acc_views = [dart.View(v.theta_deg, v.phi_deg, v.width, v.height, v.pixel_scale, v.t_obs,
+                           v.alpha, v.flags | dart.DART_ACCUMULATE) for v in views]
+    total = [torch.zeros_like(im) for im in whole_imgs]
+    scratch = [torch.empty_like(im) for im in whole_imgs]
+    flux = np.zeros(n)
+    steps = np.zeros(n, dtype=np.uint64)
+    per_slab = []
+    for a in range(k):
+        t0 = time.time()
+        st, _ = build_stack_incremental(dart, torch, dims, M, seed, gamma, knots, dart.DART_BF16,
+                                        chunk_bytes=9 << 30, z_slab=(cuts[a], cuts[a + 1] - cuts[a]))
+        gb = dart.dart_stack_get_info(st).device_bytes / 1e9
+        f, s = dart.dart_render_batch([st] * n, acc_views, total, stream=stream)
+        flux += f
+        steps += s
+
+        def one():
+            dart.dart_render_batch([st] * n, views, scratch, stream=stream, stats=False)
+
+        reps = max(1, min(args.steps, 3))
+        wall, _ = time_steps(torch, stream, one, reps, 1)
+        per_slab.append({"z": [cuts[a], cuts[a + 1]], "resident_gb": gb,
+                         "ms_per_step": 1e3 * wall / reps, "cell_steps": int(np.sum(s)),
+                         "load_s": time.time() - t0})
+        torch.cuda.synchronize()
+        dart.dart_free_epochs(st)
+    torch.cuda.synchronize()
+    perr = 0.0
+    for g, w in zip(total, whole_imgs):
+        floor = 1e-3 * float(w.abs().max())
+        e = ((g.double() - w.double()).abs() / w.double().abs().clamp_min(floor)).max()
+        perr = max(perr, float(e))
+    ferr = float(np.max(np.abs(flux - whole_flux) / np.abs(whole_flux)))
+    serr = float(np.max(np.abs(steps.astype(np.float64) - whole_steps.astype(np.float64)) /
+                        whole_steps.astype(np.float64)))
+    return {"n": k, "per_slab": per_slab, "images": n, "flux_rel_err_vs_whole": ferr,
+            "max_pixel_rel_err_vs_whole": perr, "cell_steps_rel_diff": serr,
+            "tolerance": {"flux": 1e-6, "pixel": 1e-5}}
 
 
 # --------------------------------------------------------------------------- main
@@ -531,6 +596,9 @@ def main():
     ap.add_argument("--workload", default="jet", choices=["jet", "batch", "serve", "large"])
     ap.add_argument("--large-views", type=int, default=256)
     ap.add_argument("--large-check", type=int, default=4)
+    ap.add_argument("--large-slabs", type=int, default=2,
+                    help="large workload: also render the domain as this many z-slabs "
+                         "and compare their sum with the whole (0: skip)")
     ap.add_argument("--storage", default="f16", choices=["f16", "bf16"],
                     help="batch workload: 16-bit storage type")
     ap.add_argument("--requests", type=int, default=6000)

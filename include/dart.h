@@ -75,6 +75,11 @@ typedef enum { DART_F64 = 0, DART_F32 = 1, DART_F16 = 2, DART_BF16 = 3 } dart_dt
 #define DART_DEVICE_PTRS 0x20u  /* load: field pointers are device pointers;
                                    view: the image pointer is a device pointer */
 #define DART_KERNEL_PLAIN 0x40u /* dart_render_batch: force the one-launch-per-image kernel */
+#define DART_ACCUMULATE 0x80u   /* view: add the render to the values already in the image
+                                   instead of overwriting them, so partial renders of
+                                   sub-domains sum into one buffer (Sec. 4, Fig. 5; Sec. 6.2).
+                                   Device images only (DART_DEVICE_PTRS); calls that add into
+                                   one image run in stream order; not accepted by dart_submit */
 
 typedef struct dart_stack dart_stack;
 typedef struct dart_server dart_server;
@@ -126,6 +131,15 @@ typedef struct {
     uint64_t device_bytes; /* resident bytes */
 } dart_stack_info;
 dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info *info);
+
+/* Places the stack inside a larger domain, for renders of sub-domains whose
+ * partial images add up to the render of the whole (optically thin emission
+ * is additive along a ray; the paper's partial renders of sub-regions,
+ * Sec. 6.2).  origin[3]: position of the grid's lower corner; centre[3]: the
+ * point every camera is centred on and through which the s = 0 plane of the
+ * retarded time passes (for a slab: the centre of the whole domain).
+ * Defaults: origin 0, centre = the grid's own centre.  Finite values only. */
+dart_status dart_stack_set_placement(dart_stack *s, const double origin[3], const double centre[3]);
 
 /* Re-lays the resident stack with a new brick shape (powers of two, each
  * 1..16, at most 4096 cells per brick).  Needs the stack's size again in free

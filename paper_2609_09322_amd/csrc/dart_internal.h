@@ -14,6 +14,7 @@ enum : uint32_t {
     F_NO_KAHAN = 0x8u,
     F_F64_DDA = 0x10u,
     F_DEVICE_PTRS = 0x20u,
+    F_ACCUMULATE = 0x80u,
 };
 
 // Resident stack as the kernels see it.  Records (j, bx, by, bz) are stored

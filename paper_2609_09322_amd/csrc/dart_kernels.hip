@@ -411,8 +411,14 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
 
 __device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, double val) {
     const size_t o = (size_t)pj * v.width + pi;
-    if (v.out_f64) ((double *)v.image)[o] = val;
-    else ((float *)v.image)[o] = (float)val;
+    const bool add = (v.flags & F_ACCUMULATE) != 0;
+    if (v.out_f64) {
+        double *p = (double *)v.image + o;
+        *p = add ? *p + val : val;
+    } else {
+        float *p = (float *)v.image + o;
+        *p = add ? (float)((double)*p + val) : (float)val;
+    }
 }
 
 // ------------------------------------------------------------------ kernels

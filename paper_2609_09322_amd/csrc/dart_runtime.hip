@@ -327,6 +327,21 @@ extern "C" dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_ou
     return DART_OK;
 }
 
+extern "C" dart_status dart_stack_set_placement(dart_stack *s, const double origin[3],
+                                                const double centre[3]) {
+    if (!s || !origin || !centre) return fail(DART_E_INVAL, "NULL argument");
+    for (int a = 0; a < 3; a++)
+        if (!isfinite(origin[a]) || !isfinite(centre[a]))
+            return fail(DART_E_INVAL, "origin and centre must be finite");
+    for (int a = 0; a < 3; a++) {
+        s->origin[a] = origin[a];
+        s->centre[a] = centre[a];
+    }
+    s->placed = true;
+    s->generation++;
+    return DART_OK;
+}
+
 extern "C" dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3],
                                           void *hip_stream) {
     if (!s || !brick) return fail(DART_E_INVAL, "NULL argument");
@@ -390,8 +405,11 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     if (v->out_dtype == DART_F64 && s->storage != DART_F64)
         return fail(DART_E_INVAL, "FP64 images need an FP64 stack");
     if (v->flags & ~(uint32_t)(DART_NO_LOOKBACK | DART_NO_BEAMING | DART_NEAREST_EPOCH |
-                               DART_NO_KAHAN | DART_FORCE_F64_DDA | DART_DEVICE_PTRS))
+                               DART_NO_KAHAN | DART_FORCE_F64_DDA | DART_DEVICE_PTRS |
+                               DART_ACCUMULATE))
         return fail(DART_E_INVAL, "unknown view flags 0x%x", v->flags);
+    if ((v->flags & DART_ACCUMULATE) && !(v->flags & DART_DEVICE_PTRS))
+        return fail(DART_E_INVAL, "DART_ACCUMULATE needs a device image (DART_DEVICE_PTRS)");
     memset(rv, 0, sizeof(*rv));
     double st, ct, sp, cp;
     sincos_deg(v->theta_deg, &st, &ct);
@@ -400,14 +418,17 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     for (int a = 0; a < 3; a++) {
         rv->shat[a] = -nhat[a];
         rv->inv_shat[a] = rv->shat[a] != 0.0 ? 1.0 / rv->shat[a] : 0.0;
-        rv->centre[a] = 0.5 * s->dev.n[a] * s->dev.cell[a];
+        // kernels work in grid-local coordinates: the camera centre relative
+        // to the grid's lower corner
+        rv->centre[a] = s->placed ? s->centre[a] - s->origin[a] : 0.5 * s->dev.n[a] * s->dev.cell[a];
     }
     rv->eu[0] = -sp; rv->eu[1] = cp; rv->eu[2] = 0.0;
     rv->ev[0] = -ct * cp; rv->ev[1] = -ct * sp; rv->ev[2] = st;
     rv->ps = v->pixel_scale;
     rv->t_obs = v->t_obs;
     rv->p = 2.0 + v->alpha;
-    rv->flags = v->flags & (F_NO_LOOKBACK | F_NO_BEAMING | F_NEAREST | F_NO_KAHAN | F_F64_DDA);
+    rv->flags = v->flags & (F_NO_LOOKBACK | F_NO_BEAMING | F_NEAREST | F_NO_KAHAN | F_F64_DDA |
+                            F_ACCUMULATE);
     // FP64 ray parameters (plane crossings, chord midpoints) when a ray may
     // cross more than ~4k cells, and for FP32 stacks: FP32 crossings of
     // magnitude ~L/2 carry ~1e-5 absolute rounding, which chords at jumps of
@@ -769,6 +790,17 @@ extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const 
     if (n == 0) return DART_OK;
     for (int32_t i = 0; i < n; i++)
         if (!stacks[i]) return fail(DART_E_INVAL, "stacks[%d] is NULL", i);
+    {
+        // two views of one call writing the same device image would race
+        std::vector<std::pair<const void *, int32_t>> dst;
+        for (int32_t i = 0; i < n; i++)
+            if (views[i].flags & DART_DEVICE_PTRS) dst.emplace_back(images[i], i);
+        std::sort(dst.begin(), dst.end());
+        for (size_t k = 1; k < dst.size(); k++)
+            if (dst[k].first == dst[k - 1].first)
+                return fail(DART_E_INVAL, "views %d and %d write the same image", dst[k - 1].second,
+                            dst[k].second);
+    }
     bool force_plain = false;
     for (int32_t i = 0; i < n; i++)
         if (views[i].flags & DART_KERNEL_PLAIN) force_plain = true;
@@ -902,7 +934,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
     std::vector<size_t> off(n);
     for (int32_t i = 0; i < n; i++) {
         vv[i].flags |= DART_DEVICE_PTRS;
-        vv[i].flags &= ~DART_KERNEL_PLAIN;
+        vv[i].flags &= ~(DART_KERNEL_PLAIN | DART_ACCUMULATE);
         off[i] = total;
         total += ((size_t)views[i].width * views[i].height * (views[i].out_dtype == DART_F64 ? 8 : 4) + 255) & ~(size_t)255;
     }

@@ -27,9 +27,10 @@ DART_NO_KAHAN = 0x8
 DART_FORCE_F64_DDA = 0x10
 DART_DEVICE_PTRS = 0x20
 DART_KERNEL_PLAIN = 0x40
+DART_ACCUMULATE = 0x80
 
 EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "dart_free_epochs",
-           "dart_stack_get_info", "dart_stack_rebrick", "dart_render", "dart_render_batch",
+           "dart_stack_get_info", "dart_stack_rebrick", "dart_stack_set_placement", "dart_render", "dart_render_batch",
            "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples",
            "dart_record_bytes", "dart_bandwidth_probe", "dart_server_create", "dart_submit",
            "dart_poll", "dart_wait", "dart_server_destroy", "dart_server_get_stats",
@@ -106,6 +107,7 @@ def _load():
         "dart_free_epochs": [_P],
         "dart_stack_get_info": [_P, _P],
         "dart_stack_rebrick": [_P, _P, _P],
+        "dart_stack_set_placement": [_P, _P, _P],
         "dart_render": [_P, _P, _P, _P, _P, _P],
         "dart_render_batch": [_P, _P, I32, _P, _P, _P, _P],
         "dart_autotune": [_P, _P, I32, I32, _P, _P, _P],
@@ -247,6 +249,12 @@ def dart_stack_get_info(stack: Stack) -> dart_stack_info:
 def dart_stack_rebrick(stack: Stack, brick, stream=None):
     b = (ctypes.c_int32 * 3)(*[int(v) for v in brick])
     _check(_load().dart_stack_rebrick(stack.handle, b, _stream(stream)))
+
+
+def dart_stack_set_placement(stack: Stack, origin, centre):
+    o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    c = (ctypes.c_double * 3)(*[float(v) for v in centre])
+    _check(_load().dart_stack_set_placement(stack.handle, o, c))
 
 
 def dart_record_bytes(stack: Stack) -> int:

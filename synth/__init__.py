@@ -172,7 +172,8 @@ class JetParams(ctypes.Structure):
                 ("knot_sigma", ctypes.c_float), ("knot_amp", ctypes.c_float),
                 ("turb_speed", ctypes.c_float), ("outside", ctypes.c_float),
                 ("k", ctypes.c_float * (64 * 3)), ("phase", ctypes.c_float * 64),
-                ("knot_z0", ctypes.c_float * 16)]
+                ("knot_z0", ctypes.c_float * 16),
+                ("z_begin", ctypes.c_int), ("z_count", ctypes.c_int)]
 
 
 def jet_params(dims, seed, gamma_spine=5.0, n_knots=4, n_modes=64):
@@ -192,6 +193,7 @@ def jet_params(dims, seed, gamma_spine=5.0, n_knots=4, n_modes=64):
     p.phase[:] = [float(x) for x in rng.uniform(0, 2 * math.pi, size=n_modes)] + [0.0] * (64 - n_modes)
     z0 = rng.uniform(0, nz, size=n_knots)
     p.knot_z0[:] = [float(x) for x in z0] + [0.0] * (16 - n_knots)
+    p.z_begin, p.z_count = 0, nz
     return p
 
 
@@ -233,15 +235,21 @@ def jet_fill_device(params: JetParams, times, j_ptr: int, beta_ptr: int, stream:
         raise RuntimeError(f"synth_jet_fill failed ({rc})")
 
 
-def jet_torch(dims, n_epochs, seed, gamma_spine=5.0, n_knots=4, device="cuda", times=None):
-    """Convenience: allocate float32 torch tensors on the device and fill them."""
+def jet_torch(dims, n_epochs, seed, gamma_spine=5.0, n_knots=4, device="cuda", times=None,
+              z_slab=None):
+    """Convenience: allocate float32 torch tensors on the device and fill them.
+    z_slab=(z0, nz_slab) fills only those z-layers of the domain `dims`, with
+    the same values the whole domain holds there."""
     import torch
     nx, ny, nz = dims
     if times is None:
         times = jet_times(dims, n_epochs)
+    p = jet_params(dims, seed, gamma_spine=gamma_spine, n_knots=n_knots)
+    if z_slab is not None:
+        p.z_begin, p.z_count = int(z_slab[0]), int(z_slab[1])
+        nz = p.z_count
     j = torch.empty((n_epochs, nz, ny, nx), dtype=torch.float32, device=device)
     b = torch.empty((n_epochs, nz, ny, nx, 3), dtype=torch.float32, device=device)
-    p = jet_params(dims, seed, gamma_spine=gamma_spine, n_knots=n_knots)
     jet_fill_device(p, times, j.data_ptr(), b.data_ptr(),
                     torch.cuda.current_stream().cuda_stream)
     return j, b, np.asarray(times, dtype=np.float64)

@@ -17,16 +17,17 @@ struct JetParams {
     float k[64 * 3];
     float phase[64];
     float knot_z0[16];
+    int z_begin, z_count;  // fill only the z-slab [z_begin, z_begin + z_count) of the domain
 };
 
 __global__ void __launch_bounds__(256) jet_fill_kernel(JetParams p, double t, float *__restrict__ j,
                                                        float *__restrict__ beta) {
-    const long long ncell = (long long)p.nx * p.ny * p.nz;
+    const long long ncell = (long long)p.nx * p.ny * p.z_count;
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
          c += (long long)gridDim.x * blockDim.x) {
         int ix = (int)(c % p.nx);
         int iy = (int)((c / p.nx) % p.ny);
-        int iz = (int)(c / ((long long)p.nx * p.ny));
+        int iz = p.z_begin + (int)(c / ((long long)p.nx * p.ny));
         float x = ix + 0.5f, y = iy + 0.5f, z = iz + 0.5f;
         float rx = x - 0.5f * p.nx, ry = y - 0.5f * p.ny;
         float r = sqrtf(rx * rx + ry * ry);
@@ -69,9 +70,10 @@ __global__ void __launch_bounds__(256) jet_fill_kernel(JetParams p, double t, fl
 extern "C" int synth_jet_fill(const JetParams *p, int n_epochs, const double *times, float *j,
                               float *beta, void *stream) {
     if (!p || !times || !j || !beta || n_epochs < 1 || p->nx < 1 || p->ny < 1 || p->nz < 1 ||
-        p->n_modes < 1 || p->n_modes > 64 || p->n_knots < 0 || p->n_knots > 16)
+        p->n_modes < 1 || p->n_modes > 64 || p->n_knots < 0 || p->n_knots > 16 ||
+        p->z_begin < 0 || p->z_count < 1 || p->z_begin + p->z_count > p->nz)
         return -1;
-    const long long ncell = (long long)p->nx * p->ny * p->nz;
+    const long long ncell = (long long)p->nx * p->ny * p->z_count;
     long long blocks = (ncell + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipStream_t s = (hipStream_t)stream;
