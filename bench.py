@@ -471,10 +471,19 @@ def run_large_workload(args, dart, torch):
     views = [dart.View(th, ph, 1024, 1024, L / 1024, 0.0, 0.6, flags)
              for th, ph, _ in synth.isotropic_views(args.large_views, 1005, sizes=(1024,))]
     stream = torch.cuda.Stream()
-    best, ms = dart.dart_autotune([st] * 8, views[:8], rebrick=False, stream=stream)
-    tuning = {"tile": [best.tile_w, best.tile_h], "waves_per_cu": best.waves_per_cu,
-              "order": best.order, "orient": best.orient, "brick": list(info.brick)}
-    log(f"autotune: {tuning}")
+    if args.tuning:
+        tw, th_, w, order, orient, bx, by, bz = [int(x) for x in args.tuning.split(",")]
+        dart.dart_stack_rebrick(st, (bx, by, bz), stream)
+        dart.dart_set_tuning(tw, th_, w, order, orient)
+        tuning = {"tile": [tw, th_], "waves_per_cu": w, "order": order, "orient": orient,
+                  "brick": [bx, by, bz], "fixed": True}
+    else:
+        # brick shapes are re-laid in place, one epoch at a time (no room for a copy)
+        best, ms = dart.dart_autotune([st] * 8, views[:8], rebrick=args.rebrick, stream=stream)
+        info = dart.dart_stack_get_info(st)
+        tuning = {"tile": [best.tile_w, best.tile_h], "waves_per_cu": best.waves_per_cu,
+                  "order": best.order, "orient": best.orient, "brick": list(info.brick)}
+    log(f"tuning: {tuning}")
     imgs = [torch.zeros((1024, 1024), dtype=torch.float32, device="cuda") for _ in views]
     n = len(views)
     flux, steps = dart.dart_render_batch([st] * n, views, imgs, stream=stream)
@@ -485,6 +494,10 @@ def run_large_workload(args, dart, torch):
 
     wall, per = time_steps(torch, stream, batched, args.steps, args.warmup)
     ms_step = 1e3 * wall / args.steps
+    if args.profile:
+        log(f"batched {ms_step:.1f} ms/step, {cell_steps:.3e} cell-steps")
+        return {"profile": True, "ms_per_step": ms_step, "cell_steps": cell_steps,
+                "tuning": tuning}
     pl = torch.zeros((1024, 1024), dtype=torch.float32, device="cuda")
 
     def plain():
@@ -515,7 +528,7 @@ def run_large_workload(args, dart, torch):
         torch.cuda.synchronize()
         dart.dart_free_epochs(st)
         slabs = render_slabs(args, dart, torch, dims, M, seed, gamma, knots, views, imgs, flux,
-                             steps, stream)
+                             steps, stream, brick=tuning["brick"])
         log(f"slabs: {slabs}")
     return {
         "metric": "cell-steps/s & images/s (batched vs plain kernel) at 1e-5 rel; p50/p99 ms",
@@ -537,7 +550,7 @@ def run_large_workload(args, dart, torch):
 
 
 def render_slabs(args, dart, torch, dims, M, seed, gamma, knots, views, whole_imgs, whole_flux,
-                 whole_steps, stream):
+                 whole_steps, stream, brick=None):
     """Domain slabs on one GPU: the grid is cut into z-slabs; each is loaded
     alone (the share one GPU of a slab-sharded job would hold), placed in the
     domain, and rendered with every view adding into one set of images.  The
@@ -557,6 +570,8 @@ def render_slabs(args, dart, torch, dims, M, seed, gamma, knots, views, whole_im
         t0 = time.time()
         st, _ = build_stack_incremental(dart, torch, dims, M, seed, gamma, knots, dart.DART_BF16,
                                         chunk_bytes=9 << 30, z_slab=(cuts[a], cuts[a + 1] - cuts[a]))
+        if brick is not None:
+            dart.dart_stack_rebrick(st, brick, stream)
         gb = dart.dart_stack_get_info(st).device_bytes / 1e9
         f, s = dart.dart_render_batch([st] * n, acc_views, total, stream=stream)
         flux += f

@@ -142,8 +142,12 @@ dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info *info);
 dart_status dart_stack_set_placement(dart_stack *s, const double origin[3], const double centre[3]);
 
 /* Re-lays the resident stack with a new brick shape (powers of two, each
- * 1..16, at most 4096 cells per brick).  Needs the stack's size again in free
- * device memory while it runs. */
+ * 1..16, at most 4096 cells per brick); the current shape returns at once.
+ * Uses a second copy of the stack when device memory allows, else (when the
+ * epoch size does not change) re-lays one epoch at a time in place through a
+ * one-epoch buffer.  If that in-place pass fails part-way the stack reports
+ * its epochs as unfilled and renders on it return DART_E_INVAL until they are
+ * loaded again.  Synchronises the stream. */
 dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3], void *hip_stream);
 
 /* ---------------------------------------------------------------- render --

@@ -353,13 +353,48 @@ extern "C" dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3],
     }
     if (cells > 4096) return fail(DART_E_INVAL, "brick larger than 4096 cells");
     if (stack_busy(s)) return fail(DART_E_BUSY, "renders that read this stack are in flight");
+    if (lb[0] == s->dev.lb[0] && lb[1] == s->dev.lb[1] && lb[2] == s->dev.lb[2]) return DART_OK;
     hipStream_t stream = (hipStream_t)hip_stream;
     dart_stack tmp;
     tmp.dev = s->dev;
     layout(&tmp, lb);
-    const uint64_t bytes = tmp.dev.epoch_stride * s->dev.n_epochs * record_bytes(s->dev.store);
+    const uint64_t rb = record_bytes(s->dev.store);
+    const uint64_t bytes = tmp.dev.epoch_stride * s->dev.n_epochs * rb;
     void *data = nullptr;
-    HIP_TRY(hipMalloc(&data, bytes), "hipMalloc(rebrick)");
+    hipError_t em = hipMalloc(&data, bytes);
+    if (em == hipErrorOutOfMemory && tmp.dev.epoch_stride == s->dev.epoch_stride &&
+        s->dev.n_epochs > 1) {
+        // No room for a second copy: re-lay one epoch at a time through a
+        // one-epoch buffer and copy it back in place (same epoch size).
+        (void)hipGetLastError();
+        const uint64_t eb = s->dev.epoch_stride * rb;
+        void *one = nullptr;
+        HIP_TRY(hipMalloc(&one, eb), "hipMalloc(rebrick epoch)");
+        hipError_t e = hipSuccess;
+        for (int32_t m = 0; m < s->dev.n_epochs && e == hipSuccess; m++) {
+            StackDev from = s->dev, to = tmp.dev;
+            from.data = (const char *)s->dev.data + (uint64_t)m * eb;
+            from.n_epochs = to.n_epochs = 1;
+            to.data = one;
+            e = launch_rebrick(s->dev.store, from, to, one, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync((char *)s->dev.data + (uint64_t)m * eb, one, eb,
+                                   hipMemcpyDeviceToDevice, stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        (void)hipFree(one);
+        // a failure part-way leaves epochs in mixed layouts: the stack is unusable
+        if (e != hipSuccess) {
+            for (int32_t m = 0; m < s->dev.n_epochs; m++) s->filled[m] = false;
+            s->generation++;
+            return hip_fail(e, "rebrick in place (the stack's epochs must be loaded again)");
+        }
+        tmp.dev.data = s->dev.data;
+        s->dev = tmp.dev;
+        s->generation++;
+        return DART_OK;
+    }
+    HIP_TRY(em, "hipMalloc(rebrick)");
     tmp.dev.data = data;
     hipError_t e = launch_rebrick(s->dev.store, s->dev, tmp.dev, data, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -951,7 +986,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
     // so the sweep covers low occupancies, row-like tiles and both spatial orders.
     const int shapes[][2] = {{64, 1}, {32, 2}, {16, 4}, {8, 8}};
     const int waves[] = {8, 12, 16};
-    const int orders[] = {0, 2};
+    const int orders[] = {0, 1, 2};
     for (auto &sh : shapes)
         for (int w : waves)
             for (int order : orders)
