@@ -17,7 +17,7 @@ Contents
   transverse speed (Eq. 21), flux laws and flux ratio (Eqs. 22-23), aliasing
   cadence (Eqs. 24-25).
 
-Conventions (the readings are listed in the design doc): alpha is the positive index
+Conventions (readings of the paper where it leaves them open): alpha is the positive index
 of S ~ nu^-alpha, so the per-cell exponent is p = 2 + alpha (the paper's
 2 - alpha with its alpha = -0.6 default); c = 1; theta is the polar angle of the
 direction to the observer from +z and phi its azimuth from +x, in degrees.
@@ -34,7 +34,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dart_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liborc.so")
+# DART_ORACLE_LIB points the loader at another build of dart_oracle.c (the
+# mutation tests load deliberately broken copies to show the pins catch them)
+_LIB_PATH = os.environ.get("DART_ORACLE_LIB") or os.path.join(_HERE, "liborc.so")
 
 NO_LOOKBACK = 1
 NO_BEAMING = 2

@@ -90,6 +90,10 @@ static int ilog2_exact(int v) {
     return (1 << l) == v ? l : -1;
 }
 
+#ifndef DART_EPOCH_PAD_RECORDS
+#define DART_EPOCH_PAD_RECORDS 0
+#endif
+
 static void layout(dart_stack *s, const int lb[3]) {
     uint64_t per = 1;
     for (int a = 0; a < 3; a++) {
@@ -97,7 +101,7 @@ static void layout(dart_stack *s, const int lb[3]) {
         s->dev.nb[a] = (s->dev.n[a] + (1 << lb[a]) - 1) >> lb[a];
         per *= (uint64_t)s->dev.nb[a] << lb[a];
     }
-    s->dev.epoch_stride = per;
+    s->dev.epoch_stride = per + DART_EPOCH_PAD_RECORDS;
 }
 
 static void default_brick(int store, int lb[3]) {
