@@ -90,10 +90,6 @@ static int ilog2_exact(int v) {
     return (1 << l) == v ? l : -1;
 }
 
-#ifndef DART_EPOCH_PAD_RECORDS
-#define DART_EPOCH_PAD_RECORDS 0
-#endif
-
 static void layout(dart_stack *s, const int lb[3]) {
     uint64_t per = 1;
     for (int a = 0; a < 3; a++) {
@@ -101,7 +97,7 @@ static void layout(dart_stack *s, const int lb[3]) {
         s->dev.nb[a] = (s->dev.n[a] + (1 << lb[a]) - 1) >> lb[a];
         per *= (uint64_t)s->dev.nb[a] << lb[a];
     }
-    s->dev.epoch_stride = per + DART_EPOCH_PAD_RECORDS;
+    s->dev.epoch_stride = per;
 }
 
 static void default_brick(int store, int lb[3]) {
