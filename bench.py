@@ -22,6 +22,7 @@ Prints one JSON line (rank 0).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -34,10 +35,68 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "k_batch_traffic.txt")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_id():
+    """Identity of the render kernels' source: counter measurements taken on
+    other sources do not describe the kernel that runs."""
+    h = hashlib.sha256()
+    for f in ("dart_kernels.hip", "dart_internal.h"):
+        with open(os.path.join(ROOT, "paper_2609_09322_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def tuning_key(t):
+    """The --tuning string of a launch shape: tile_w,tile_h,waves_per_cu,order,
+    orient,brick_x,brick_y,brick_z,depth_sync."""
+    return ",".join(str(x) for x in (t["tile"][0], t["tile"][1], t["waves_per_cu"], t["order"],
+                                     t["orient"], *t["brick"], t.get("depth_sync", 0)))
+
+
+def tuning_dict(best, info):
+    return {"tile": [best.tile_w, best.tile_h], "waves_per_cu": best.waves_per_cu,
+            "order": best.order, "orient": best.orient, "brick": list(info.brick),
+            "depth_sync": best.depth_sync}
+
+
+def apply_fixed_tuning(dart, st, spec, stream):
+    f = normalise_tuning(spec)
+    tw, th_, w, order, orient, bx, by, bz, sync = [int(x) for x in f.split(",")]
+    dart.dart_stack_rebrick(st, (bx, by, bz), stream)
+    dart.dart_set_tuning(tw, th_, w, order, orient, sync)
+    return {"tile": [tw, th_], "waves_per_cu": w, "order": order, "orient": orient,
+            "brick": [bx, by, bz], "depth_sync": sync, "fixed": True}
+
+
+def normalise_tuning(spec):
+    """--tuning with the optional depth_sync field filled in (0)."""
+    return spec + ",0" if spec.count(",") == 7 else spec
+
+
+def measured_traffic(workload, tuning):
+    """HBM bytes per k_batch launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed counter table, when it holds a row for this workload,
+    this kernel source and this launch shape; otherwise None and the reason."""
+    if not tuning:
+        return None, "no launch shape"
+    key, kid = tuning_key(tuning), kernel_source_id()
+    rows = []
+    if os.path.exists(TRAFFIC_TABLE):
+        with open(TRAFFIC_TABLE) as fh:
+            for ln in fh:
+                f = ln.split()
+                if len(f) >= 5 and not ln.startswith("#"):
+                    rows.append(f)
+    for f in rows:
+        if f[0] == workload and f[1] == kid and f[2] == key:
+            return float(f[3]) + float(f[4]), f"counters for {workload}, tuning {key}, kernel {kid}"
+    return None, f"no counter row for {workload}, tuning {key}, kernel {kid}"
 
 
 def pct(xs, q):
@@ -145,6 +204,7 @@ def pix_err(got, ref, img_max):
 def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_spec, gamma,
                         knots, seed, rec_bytes, dtype_name, check_views=None, tune_views=None):
     stream = torch.cuda.Stream()
+    wkey = args.workload if args.workload != "batch" else f"batch-{args.storage}"
     keep_host = not args.no_cpu_baseline or args.check
     st, times, host = make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage,
                                      dtype_name, keep_host)
@@ -156,20 +216,14 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
 
     tuning = None
     if args.tuning:
-        tw, th_, w, order, orient, bx, by, bz = [int(x) for x in args.tuning.split(",")]
-        dart.dart_stack_rebrick(st, (bx, by, bz), stream)
-        dart.dart_set_tuning(tw, th_, w, order, orient)
-        tuning = {"tile": [tw, th_], "waves_per_cu": w, "order": order, "orient": orient,
-                  "brick": [bx, by, bz], "fixed": True}
+        tuning = apply_fixed_tuning(dart, st, args.tuning, stream)
         log(f"fixed tuning: {tuning}")
     elif args.autotune:
         t0 = time.time()
         tv = views if tune_views is None else views[:tune_views]
         best, ms = dart.dart_autotune([st] * len(tv), tv, rebrick=args.rebrick, stream=stream)
-        info = dart.dart_stack_get_info(st)
-        tuning = {"tile": [best.tile_w, best.tile_h], "waves_per_cu": best.waves_per_cu,
-                  "order": best.order, "orient": best.orient, "brick": list(info.brick),
-                  "best_ms": ms, "tune_s": time.time() - t0}
+        tuning = tuning_dict(best, dart.dart_stack_get_info(st))
+        tuning.update(best_ms=ms, tune_s=time.time() - t0)
         log(f"autotune ({time.time() - t0:.1f} s): {tuning}")
 
     # untimed: cell-steps and flux of every image, compulsory samples
@@ -179,7 +233,10 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
     samples = [dart.dart_count_samples(st, v, stream) for v in views] if not args.profile else []
     out_bytes = sum(4 * v.width * v.height for v in views)
     compulsory = (sum(samples) * rec_bytes + out_bytes) if samples else None
-    log(f"{n_img} images, {cell_steps:.4e} cell-steps per step, samples {sum(samples) if samples else 'n/a'}")
+    lines = [dart.dart_count_lines(st, v, stream) for v in views] if not args.profile else []
+    line_bytes = (sum(lines) * 128 + out_bytes) if lines else None
+    log(f"{n_img} images, {cell_steps:.4e} cell-steps per step, samples {sum(samples) if samples else 'n/a'}, "
+        f"lines {sum(lines) if lines else 'n/a'}")
 
     def batched():
         dart.dart_render_batch(stacks, views, imgs, stream=stream, stats=False)
@@ -238,15 +295,22 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
     achieved = compulsory / (kernel_ms * 1e-3) / 1e9 if compulsory else None
     roof = None
     if achieved is not None:
+        traffic, tsrc = measured_traffic(wkey, tuning)
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tsrc,
+                "traffic_gbs": traffic / (kernel_ms * 1e-3) / 1e9 if traffic else None,
                 "kernel": "k_batch (persistent tile-queue render)",
                 "bytes_per_launch": compulsory,
                 "bytes_definition": "distinct (cell, epoch) records with positive weight x record "
                                     "bytes + image bytes",
                 "measured_copy_gbs": bw,
                 "frac_of_measured_copy": (achieved / bw) if bw else None,
-                "gather_bytes_gbs": cell_steps * 2 * rec_bytes / (kernel_ms * 1e-3) / 1e9}
+                "gather_bytes_gbs": cell_steps * 2 * rec_bytes / (kernel_ms * 1e-3) / 1e9,
+                "line_bytes_per_launch": line_bytes,
+                "line_bytes_definition": "distinct 128-B lines of the resident layout holding "
+                                         "those records x 128 + image bytes (the fewest bytes "
+                                         "a line-granular fetch of this layout can move)",
+                "line_gbs": line_bytes / (kernel_ms * 1e-3) / 1e9 if line_bytes else None}
     value = cell_steps / (ms_step * 1e-3)
     line = {
         "metric": "cell-steps/s & images/s (batched vs plain kernel) at 1e-5 rel; p50/p99 ms",
@@ -472,17 +536,11 @@ def run_large_workload(args, dart, torch):
              for th, ph, _ in synth.isotropic_views(args.large_views, 1005, sizes=(1024,))]
     stream = torch.cuda.Stream()
     if args.tuning:
-        tw, th_, w, order, orient, bx, by, bz = [int(x) for x in args.tuning.split(",")]
-        dart.dart_stack_rebrick(st, (bx, by, bz), stream)
-        dart.dart_set_tuning(tw, th_, w, order, orient)
-        tuning = {"tile": [tw, th_], "waves_per_cu": w, "order": order, "orient": orient,
-                  "brick": [bx, by, bz], "fixed": True}
+        tuning = apply_fixed_tuning(dart, st, args.tuning, stream)
     else:
         # brick shapes are re-laid in place, one epoch at a time (no room for a copy)
         best, ms = dart.dart_autotune([st] * 8, views[:8], rebrick=args.rebrick, stream=stream)
-        info = dart.dart_stack_get_info(st)
-        tuning = {"tile": [best.tile_w, best.tile_h], "waves_per_cu": best.waves_per_cu,
-                  "order": best.order, "orient": best.orient, "brick": list(info.brick)}
+        tuning = tuning_dict(best, dart.dart_stack_get_info(st))
     log(f"tuning: {tuning}")
     imgs = [torch.zeros((1024, 1024), dtype=torch.float32, device="cuda") for _ in views]
     n = len(views)
@@ -509,6 +567,8 @@ def run_large_workload(args, dart, torch):
     log(f"batched {ms_step:.1f} ms/step, plain {pms:.1f} ms/step, {cell_steps:.3e} cell-steps")
     samples = [dart.dart_count_samples(st, v, stream) for v in views[:4]]
     est_compulsory = (sum(samples) / 4 * n) * 8 + n * 4 * 1024 * 1024
+    lines = [dart.dart_count_lines(st, v, stream) for v in views[:4]]
+    est_lines = (sum(lines) / 4 * n) * 128 + n * 4 * 1024 * 1024
     acc = None
     if args.check:
         t1 = time.time()
@@ -523,6 +583,7 @@ def run_large_workload(args, dart, torch):
                "tolerance": {"flux": 1e-6, "pixel": 2e-3}}
         log(f"oracle check: {acc}")
     achieved = est_compulsory / (float(np.mean(per)) * 1e-3) / 1e9
+    traffic, tsrc = measured_traffic("large", tuning)
     slabs = None
     if args.large_slabs > 1:
         torch.cuda.synchronize()
@@ -543,8 +604,10 @@ def run_large_workload(args, dart, torch):
         "plain": {"ms_per_step": pms, "images_per_s": n / (pms * 1e-3)},
         "speedup_images_per_s_vs_plain": pms / ms_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_definition": "compulsory records estimated from 4 counted views"},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tsrc,
+                     "bytes_definition": "compulsory records estimated from 4 counted views",
+                     "line_bytes_per_launch": est_lines,
+                     "line_gbs": est_lines / (float(np.mean(per)) * 1e-3) / 1e9},
         "accuracy": acc, "tuning": tuning, "cpu_baseline": None, "slabs": slabs,
     }
 
@@ -601,6 +664,39 @@ def render_slabs(args, dart, torch, dims, M, seed, gamma, knots, views, whole_im
             "tolerance": {"flux": 1e-6, "pixel": 1e-5}}
 
 
+# --------------------------------------------------------------------------- counters
+
+def pmc_summary(fetch_csv, write_csv, workload, tuning):
+    """One row of the traffic table from two rocprofv3 --pmc runs of
+    `bench.py --profile` (FETCH_SIZE in the first, WRITE_SIZE in the second).
+    Both counters are in KiB per dispatch; each is scaled by what it reads for
+    the 1 GiB k_copy that the profile run launches (1 GiB read, 1 GiB written)."""
+    import csv
+    import collections
+
+    def load(path):
+        agg = collections.defaultdict(list)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in agg.items()}
+
+    def pick(d, kernel, counter):
+        vals = [v for (k, c), v in d.items() if kernel in k and c == counter]
+        if len(vals) != 1:
+            raise SystemExit(f"expected one {kernel} kernel with {counter}, found {len(vals)}")
+        return vals[0]
+
+    a, b = load(fetch_csv), load(write_csv)
+    gib_kib = float(1 << 20)
+    fscale = gib_kib / pick(a, "k_copy", "FETCH_SIZE")
+    wscale = gib_kib / pick(b, "k_copy", "WRITE_SIZE")
+    fetch = pick(a, "k_batch", "FETCH_SIZE") * 1024 * fscale
+    write = pick(b, "k_batch", "WRITE_SIZE") * 1024 * wscale
+    print(f"# FETCH_SIZE scale {fscale:.4f}, WRITE_SIZE scale {wscale:.4f}")
+    print(f"{workload} {kernel_source_id()} {tuning} {fetch:.0f} {write:.0f}")
+
+
 # --------------------------------------------------------------------------- main
 
 def main():
@@ -629,10 +725,18 @@ def main():
     ap.add_argument("--no-rebrick", dest="rebrick", action="store_false", default=True)
     ap.add_argument("--tuning", default=None,
                     help="fixed launch shape instead of autotuning: "
-                         "tile_w,tile_h,waves_per_cu,order,orient,brick_x,brick_y,brick_z")
+                         "tile_w,tile_h,waves_per_cu,order,orient,brick_x,brick_y,brick_z"
+                         "[,depth_sync]")
     ap.add_argument("--profile", action="store_true",
                     help="timed batched loop only (for rocprofv3 runs)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the traffic-table row for two rocprofv3 --pmc counter files "
+                         "of a --profile run (with the same --workload/--storage/--tuning)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        wkey = args.workload if args.workload != "batch" else f"batch-{args.storage}"
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], wkey, normalise_tuning(args.tuning))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)

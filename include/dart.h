@@ -199,6 +199,10 @@ typedef struct {
     int32_t orient;          /* 1: per view, turn the tile so that its long side follows
                                 the image-plane projection of the bricks' long axis
                                 (lanes of a wavefront then share cache lines) */
+    int32_t depth_sync;      /* 0: each ray walks its own cells; n > 0: the rays of a
+                                wavefront march together, no ray more than n cell
+                                lengths (largest cell side) ahead of the rearmost, so
+                                neighbouring rays read shared lines at the same time */
 } dart_tuning;
 
 /* Times the batched kernel on the given views over candidate tile shapes,
@@ -216,6 +220,13 @@ dart_status dart_get_tuning(dart_tuning *t);
  * times the record size.  Untimed instrumentation (bitmap + counting pass). */
 dart_status dart_count_samples(const dart_stack *s, const dart_view *v, uint64_t *samples_out,
                                void *hip_stream);
+
+/* Number of distinct 128-byte lines of the stack's current layout that hold
+ * those samples: times 128 it is the fewest bytes a render of the view can
+ * fetch at cache-line granularity with this brick shape.  Untimed
+ * instrumentation, as above. */
+dart_status dart_count_lines(const dart_stack *s, const dart_view *v, uint64_t *lines_out,
+                             void *hip_stream);
 
 /* Bytes of one resident record (j, beta_x, beta_y, beta_z) of a stack. */
 dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_out);

@@ -45,6 +45,7 @@ struct RayView {
     int32_t width, height;
     int32_t fixed_m;        // NO_LOOKBACK: epoch bracket at t_obs (-1: t_obs outside coverage)
     double fixed_w;         // NO_LOOKBACK: weight of epoch fixed_m + 1
+    double sync_gap;        // batched kernel: depth-synchronous horizon (length), 0 = off
     void *image;            // [height][width] float or double (device)
     int32_t out_f64;
     int32_t acc_index;      // slot in the flux / step accumulators
@@ -71,9 +72,10 @@ struct BatchLaunch {
 // Host-side launchers (dart_kernels.hip).
 hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *step_acc,
                         hipStream_t s);
-hipError_t launch_batch(int store, bool f64_dda, const BatchLaunch &bl, int grid_blocks,
+// mode 0: each ray on its own; 1: depth-synchronous wavefronts
+hipError_t launch_batch(int store, bool f64_dda, int mode, const BatchLaunch &bl, int grid_blocks,
                         hipStream_t s);
-hipError_t launch_mark(const RayView &v, uint32_t *bitmap, hipStream_t s);
+hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *bitmap, uint64_t words, unsigned long long *out,
                            hipStream_t s);
 hipError_t launch_convert(int src_f64, int store, const void *j, const void *beta, int32_t m0,

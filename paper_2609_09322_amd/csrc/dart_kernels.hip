@@ -241,8 +241,12 @@ __device__ __forceinline__ void bracket_seek(const RayView &v, R mid, Bracket<R>
 
 // Sample marking for the compulsory-bytes count: sets the (epoch, cell) bits
 // of positive weight in `bitmap` ([M][nz][ny][nx] bits).
+// line_log2 >= 0 marks instead the 128-byte lines of the resident layout that
+// hold those records (2^line_log2 records per line): bit (record index in the
+// stack) >> line_log2.
 template <typename R>
-__device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint32_t *bitmap) {
+__device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint32_t *bitmap,
+                                         int line_log2) {
     Ray<R> r;
     if (!ray_setup(v, pi, pj, r)) return;
     const StackDev &st = v.st;
@@ -268,13 +272,21 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
                 const bool later = lookback ? (mid - br.am1) < (br.am - mid) : wt > (R)0.5;
                 m0 = later ? br.m + 1 : br.m;
             }
-            const uint64_t lin = ((uint64_t)r.z * st.n[1] + r.y) * st.n[0] + r.x;
+            uint64_t lin, stride;
+            if (line_log2 < 0) {
+                lin = ((uint64_t)r.z * st.n[1] + r.y) * st.n[0] + r.x;
+                stride = ncell;
+            } else {
+                lin = cell_offset(st, r.x, r.y, r.z);
+                stride = st.epoch_stride;
+            }
+            const int sh = line_log2 < 0 ? 0 : line_log2;
             if (single || wt < (R)1) {
-                const uint64_t b = (uint64_t)m0 * ncell + lin;
+                const uint64_t b = ((uint64_t)m0 * stride + lin) >> sh;
                 atomicOr(&bitmap[b >> 5], 1u << (b & 31));
             }
             if (!single && wt > (R)0) {
-                const uint64_t b = (uint64_t)(m0 + 1) * ncell + lin;
+                const uint64_t b = ((uint64_t)(m0 + 1) * stride + lin) >> sh;
                 atomicOr(&bitmap[b >> 5], 1u << (b & 31));
             }
         }
@@ -296,14 +308,31 @@ constexpr int CELLS_PER_BATCH = DART_CELLS_PER_BATCH;
 // batch of cells (chord, epoch weight, record addresses), then requests the
 // 2 x CELLS_PER_BATCH records at once and consumes them after a single wait:
 // many gathers per lane in flight instead of one dependent load per step.
-template <int S, typename R>
-__device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32_t &nsteps) {
+template <typename R>
+__device__ __forceinline__ R wave_min(R x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+// Marching modes (SYNC):
+//   0  each lane walks its own ray, K cells per batch;
+//   1  depth-synchronous wavefront: a batch only takes cells whose entry lies
+//      within v.sync_gap of the wavefront's rearmost ray, so neighbouring
+//      rays reach the cells (and cache lines) they share at the same time
+//      instead of some batches apart.  Every lane then stays in the loop
+//      until all rays of the wavefront have ended, including lanes whose ray
+//      misses the grid.
+template <int S, typename R, int SYNC>
+__device__ __forceinline__ double march(const RayView &v, int pi, int pj, bool in_image,
+                                        uint32_t &nsteps) {
     using A = typename std::conditional<S == ST_F64, double, float>::type;
     using Raw = typename RecT<S>::raw;
     using GRaw = const Raw __attribute__((address_space(1)));
     constexpr int K = CELLS_PER_BATCH;
     Ray<R> r;
-    if (!ray_setup(v, pi, pj, r)) return 0.0;
+    bool alive = in_image && ray_setup(v, pi, pj, r);
+    if (SYNC == 0 && !alive) return 0.0;
     const StackDev &st = v.st;
     const bool lookback = !(v.flags & F_NO_LOOKBACK);
     const bool beaming = !(v.flags & F_NO_BEAMING);
@@ -311,6 +340,7 @@ __device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32
     const bool single = (v.flags & F_NEAREST) || M == 1;
     const bool kahan = !(v.flags & F_NO_KAHAN);
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
+    const R gap = (R)v.sync_gap;
     GRaw *gdata = (GRaw *)st.data;
     const uint64_t estride = st.epoch_stride;
     // offset of the second record: the next epoch, or the same record when
@@ -322,22 +352,32 @@ __device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32
     int ebase_m = br.m;
     A sum = 0, comp = 0;
     uint32_t count = 0;
-    bool alive = true;
+    // a ray crosses at most n0 + n1 + n2 - 2 cells
+    int budget = st.n[0] + st.n[1] + st.n[2] + 3;
 
-    for (int guard = (st.n[0] + st.n[1] + st.n[2]) / K + 3; guard > 0 && alive; guard--) {
+    for (;;) {
+        R front = (R)0;
+        if (SYNC != 0) {
+            front = wave_min(alive ? fmax(r.sb0, fmax(r.sb1, r.sb2)) : (R)INFINITY);
+            if (front == (R)INFINITY) break;  // uniform: every ray has ended
+        } else if (!alive) {
+            break;
+        }
         GRaw *addr[K];
         R cds[K], cw[K];
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            addr[k] = gdata;  // a valid address for cells past the end of the ray
+            addr[k] = gdata;  // a valid address for cells not taken in this batch
             cds[k] = (R)0;
             cw[k] = (R)0;
             if (alive) {
                 const R entry = fmax(r.sb0, fmax(r.sb1, r.sb2));
                 const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
-                if (entry >= r.stop) {
+                if (entry >= r.stop || budget <= 0) {
                     alive = false;
-                } else {
+                } else if (SYNC == 0 || entry - front < gap || entry <= front) {
+                    // (the rearmost ray has entry == front, so each batch
+                    // takes at least one cell or ends a ray)
                     const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
                     const bool contrib = ds > (R)0 && mid >= r_lo && mid <= r_hi;
                     R wt = (R)v.fixed_w;
@@ -362,6 +402,7 @@ __device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32
                     cds[k] = contrib ? ds : (R)0;
                     cw[k] = wt;
                     count += contrib ? 1u : 0u;
+                    budget--;
                     alive = ray_advance(st, r);
                 }
             }
@@ -372,17 +413,19 @@ __device__ __forceinline__ double march(const RayView &v, int pi, int pj, uint32
             r0[k] = load_grec<S>(addr[k]);
             r1[k] = load_grec<S>(addr[k] + second);
         }
-        // Every lane consumes all K cells: a cell past the end of the ray or
-        // outside the window has ds = 0 (its records, validated at load, are
-        // finite), and an unconditional use keeps the compiler from sinking
-        // the loads back into a branch.
+        // Every lane consumes all K cells: a cell not taken, past the end of
+        // the ray or outside the window has ds = 0 (its records, validated at
+        // load, are finite), and an unconditional use keeps the compiler from
+        // sinking the loads back into a branch.
 #pragma unroll
         for (int k = 0; k < K; k++) {
             A val = (A)boosted<S>(r0[k], v, beaming);
             const A b1 = (A)boosted<S>(r1[k], v, beaming);
             val = val + (A)cw[k] * (b1 - val);
             const A term = (A)cds[k] * val;
-            if (kahan) {
+            // a zero term leaves the compensated sum as it is, so cells not
+            // taken in a batch do not perturb it (rounding of sum - comp)
+            if (kahan && term != (A)0) {
                 const A yk = term - comp;
                 const A tk = sum + yk;
                 comp = (tk - sum) - yk;
@@ -433,7 +476,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
     uint32_t ns = 0;
     if (idx < npix) {
         const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
-        val = march<S, R>(v, pi, pj, ns);
+        val = march<S, R, 0>(v, pi, pj, true, ns);
         store_pixel(v, pi, pj, val);
     }
     const double fs = wave_sum(val);
@@ -449,7 +492,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
 // chunks; a wave starts on chunk (block index mod n_queues), which under
 // round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
 // the other chunks when its own runs dry.
-template <int S, typename R>
+template <int S, typename R, int SYNC>
 __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
     const int lane = threadIdx.x & 63;
     const uint32_t nq = bl.n_queues;
@@ -473,12 +516,10 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
                        (lane & ((1 << tw_log2) - 1));
         const int pj = (int)(__builtin_amdgcn_readfirstlane(tile.ty) << (6 - tw_log2)) +
                        (lane >> tw_log2);
-        double val = 0.0;
         uint32_t ns = 0;
-        if (pi < v.width && pj < v.height) {
-            val = march<S, R>(v, pi, pj, ns);
-            store_pixel(v, pi, pj, val);
-        }
+        const bool in_image = pi < v.width && pj < v.height;
+        const double val = march<S, R, SYNC>(v, pi, pj, in_image, ns);
+        if (in_image) store_pixel(v, pi, pj, val);
         const double fs = wave_sum(val);
         const uint32_t cs = wave_sum_u32(ns);
         if (lane == 0) {
@@ -490,11 +531,11 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
 
 // Sample marking for the compulsory-bytes count (untimed instrumentation).
 template <int S, typename R>
-__global__ void __launch_bounds__(256) k_mark(RayView v, uint32_t *bitmap) {
+__global__ void __launch_bounds__(256) k_mark(RayView v, uint32_t *bitmap, int line_log2) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long npix = (long long)v.width * v.height;
     if (idx >= npix) return;
-    mark_ray<R>(v, (int)(idx % v.width), (int)(idx / v.width), bitmap);
+    mark_ray<R>(v, (int)(idx % v.width), (int)(idx / v.width), bitmap, line_log2);
 }
 
 __global__ void __launch_bounds__(256) k_popcount(const uint32_t *bm, uint64_t words,
@@ -638,43 +679,45 @@ hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *
 }
 
 template <int S, typename R>
-static hipError_t batch_impl(const BatchLaunch &bl, int grid_blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_batch<S, R>), dim3((unsigned)grid_blocks), dim3(256), 0, s, bl);
+static hipError_t batch_impl(const BatchLaunch &bl, int mode, int grid_blocks, hipStream_t s) {
+    const dim3 g((unsigned)grid_blocks), b(256);
+    if (mode == 1) hipLaunchKernelGGL((k_batch<S, R, 1>), g, b, 0, s, bl);
+    else hipLaunchKernelGGL((k_batch<S, R, 0>), g, b, 0, s, bl);
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int store, bool f64, const BatchLaunch &bl, int grid_blocks,
+hipError_t launch_batch(int store, bool f64, int mode, const BatchLaunch &bl, int grid_blocks,
                         hipStream_t s) {
     switch (store) {
-        case ST_F64: return batch_impl<ST_F64, double>(bl, grid_blocks, s);
-        case ST_F32: return f64 ? batch_impl<ST_F32, double>(bl, grid_blocks, s)
-                                : batch_impl<ST_F32, float>(bl, grid_blocks, s);
-        case ST_F16: return f64 ? batch_impl<ST_F16, double>(bl, grid_blocks, s)
-                                : batch_impl<ST_F16, float>(bl, grid_blocks, s);
-        case ST_BF16: return f64 ? batch_impl<ST_BF16, double>(bl, grid_blocks, s)
-                                 : batch_impl<ST_BF16, float>(bl, grid_blocks, s);
+        case ST_F64: return batch_impl<ST_F64, double>(bl, mode, grid_blocks, s);
+        case ST_F32: return f64 ? batch_impl<ST_F32, double>(bl, mode, grid_blocks, s)
+                                : batch_impl<ST_F32, float>(bl, mode, grid_blocks, s);
+        case ST_F16: return f64 ? batch_impl<ST_F16, double>(bl, mode, grid_blocks, s)
+                                : batch_impl<ST_F16, float>(bl, mode, grid_blocks, s);
+        case ST_BF16: return f64 ? batch_impl<ST_BF16, double>(bl, mode, grid_blocks, s)
+                                 : batch_impl<ST_BF16, float>(bl, mode, grid_blocks, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <int S, typename R>
-static hipError_t mark_impl(const RayView &v, uint32_t *bitmap, hipStream_t s) {
+static hipError_t mark_impl(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s) {
     const uint64_t npix = (uint64_t)v.width * v.height;
     hipLaunchKernelGGL((k_mark<S, R>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, v,
-                       bitmap);
+                       bitmap, line_log2);
     return hipGetLastError();
 }
 
-hipError_t launch_mark(const RayView &v, uint32_t *bitmap, hipStream_t s) {
+hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s) {
     const bool f64 = (v.flags & F_F64_DDA) != 0;
     switch (v.st.store) {
-        case ST_F64: return mark_impl<ST_F64, double>(v, bitmap, s);
-        case ST_F32: return f64 ? mark_impl<ST_F32, double>(v, bitmap, s)
-                                : mark_impl<ST_F32, float>(v, bitmap, s);
-        case ST_F16: return f64 ? mark_impl<ST_F16, double>(v, bitmap, s)
-                                : mark_impl<ST_F16, float>(v, bitmap, s);
-        case ST_BF16: return f64 ? mark_impl<ST_BF16, double>(v, bitmap, s)
-                                 : mark_impl<ST_BF16, float>(v, bitmap, s);
+        case ST_F64: return mark_impl<ST_F64, double>(v, bitmap, line_log2, s);
+        case ST_F32: return f64 ? mark_impl<ST_F32, double>(v, bitmap, line_log2, s)
+                                : mark_impl<ST_F32, float>(v, bitmap, line_log2, s);
+        case ST_F16: return f64 ? mark_impl<ST_F16, double>(v, bitmap, line_log2, s)
+                                : mark_impl<ST_F16, float>(v, bitmap, line_log2, s);
+        case ST_BF16: return f64 ? mark_impl<ST_BF16, double>(v, bitmap, line_log2, s)
+                                 : mark_impl<ST_BF16, float>(v, bitmap, line_log2, s);
     }
     return hipErrorInvalidValue;
 }

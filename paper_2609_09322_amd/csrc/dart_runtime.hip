@@ -610,7 +610,7 @@ extern "C" dart_status dart_render(const dart_stack *s, const dart_view *v, void
 // ------------------------------------------------------------------ tuning
 
 static std::mutex g_tune_mu;
-static dart_tuning g_tuning = {32, 2, 8, 0, 1};
+static dart_tuning g_tuning = {32, 2, 8, 0, 1, 0};
 
 static dart_status check_tuning(const dart_tuning *t) {
     if (!t) return fail(DART_E_INVAL, "tuning is NULL");
@@ -622,6 +622,9 @@ static dart_status check_tuning(const dart_tuning *t) {
         return fail(DART_E_INVAL, "waves_per_cu must be a multiple of 4 in [4, 64]");
     if (t->order < 0 || t->order > 2) return fail(DART_E_INVAL, "order must be 0, 1 or 2");
     if (t->orient != 0 && t->orient != 1) return fail(DART_E_INVAL, "orient must be 0 or 1");
+    if (t->depth_sync < 0 || t->depth_sync > 64)
+        return fail(DART_E_INVAL, "depth_sync must be in [0, 64]");
+
     return DART_OK;
 }
 
@@ -708,6 +711,9 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             if (elongated && long_u != axis_u) lw = 6 - lw0;
         }
         rv.tile_w_log2 = lw;
+        rv.sync_gap = tun.depth_sync > 0
+                          ? tun.depth_sync * std::max(rv.st.cell[0], std::max(rv.st.cell[1], rv.st.cell[2]))
+                          : 0.0;
         g.views.push_back(rv);
         const int tw = 1 << lw, th = 64 >> lw;
         const int ntx = (rv.width + tw - 1) / tw, nty = (rv.height + th - 1) / th;
@@ -790,7 +796,8 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
         bl.n_queues = g.n_queues;
         bl.flux_acc = (double *)acc;
         bl.step_acc = acc + n;
-        e = launch_batch(g.store, g.f64, bl, blocks, stream);
+        const int mode = tun.depth_sync > 0 ? 1 : 0;
+        e = launch_batch(g.store, g.f64, mode, bl, blocks, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -991,7 +998,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         for (int w : waves)
             for (int order : orders)
                 for (int orient = 0; orient < 2; orient++)
-                    cands.push_back({sh[0], sh[1], w, order, orient});
+                    cands.push_back({sh[0], sh[1], w, order, orient, 0});
     // Brick candidates: every power-of-two shape holding one 128-B cache line
     // of records.  Which one wins depends on the view set: lines that extend
     // along the rays' directions are used whole by one ray, lines across the
@@ -1039,40 +1046,72 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         }
         return DART_OK;
     };
+    // Candidates within 1% of the fastest count as ties (timing noise); a tie
+    // goes to the earliest candidate in the sweep order, so repeated tunings of
+    // one workload settle on the same choice.
+    auto pick = [](const std::vector<float> &ms) {
+        const float lo = *std::min_element(ms.begin(), ms.end());
+        for (size_t k = 0; k < ms.size(); k++)
+            if (ms[k] <= 1.01f * lo) return k;
+        return (size_t)0;
+    };
     double best_ms = INFINITY;
     dart_tuning best = saved;
     dart_status result = DART_OK;
     // Stage 1: brick shapes under a few representative launch shapes.
-    std::array<int, 3> best_brick = {0, 0, 0};
     if (rebrick) {
-        const dart_tuning probes[] = {{64, 1, 12, 0, 0}, {64, 1, 12, 0, 1}, {8, 8, 12, 0, 0}};
+        const dart_tuning probes[] = {{64, 1, 12, 0, 0, 0}, {64, 1, 12, 0, 1, 0},
+                                      {8, 8, 12, 0, 0, 0}};
+        std::vector<float> brick_ms;
         for (auto &br : bricks) {
             result = rebrick_all(br);
             if (result != DART_OK) break;
+            float b_ms = INFINITY;
             for (const dart_tuning &c : probes) {
                 float ms = 0;
                 result = measure(c, &ms);
                 if (result != DART_OK) break;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = c;
-                    best_brick = br;
-                }
+                b_ms = std::min(b_ms, ms);
             }
             if (result != DART_OK) break;
+            brick_ms.push_back(b_ms);
         }
-        if (result == DART_OK) result = rebrick_all(best_brick);
+        if (result == DART_OK) result = rebrick_all(bricks[pick(brick_ms)]);
     }
     // Stage 2: launch shapes on the chosen layout.
     if (result == DART_OK) {
+        std::vector<float> cand_ms;
         for (const dart_tuning &c : cands) {
             float ms = 0;
             result = measure(c, &ms);
             if (result != DART_OK) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c;
-            }
+            cand_ms.push_back(ms);
+        }
+        if (result == DART_OK) {
+            const size_t k = pick(cand_ms);
+            best = cands[k];
+            best_ms = cand_ms[k];
+        }
+    }
+    // Stage 3: depth-synchronous marching on the chosen launch shape.
+    if (result == DART_OK) {
+        std::vector<dart_tuning> c3;
+        std::vector<float> c3_ms;
+        c3.push_back(best);
+        c3_ms.push_back((float)best_ms);
+        for (int gap : {1, 2, 3, 4, 6}) {
+            dart_tuning c = best;
+            c.depth_sync = gap;
+            float ms = 0;
+            result = measure(c, &ms);
+            if (result != DART_OK) break;
+            c3.push_back(c);
+            c3_ms.push_back(ms);
+        }
+        if (result == DART_OK) {
+            const size_t k = pick(c3_ms);
+            best = c3[k];
+            best_ms = c3_ms[k];
         }
     }
     for (int32_t i = 0; i < n; i++) {
@@ -1091,29 +1130,47 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
 
 // ------------------------------------------------------------------ counting / probe
 
-extern "C" dart_status dart_count_samples(const dart_stack *s, const dart_view *v,
-                                          uint64_t *samples_out, void *hip_stream) {
-    if (!samples_out) return fail(DART_E_INVAL, "samples_out is NULL");
+// Distinct marked bits over one view: records (line_log2 < 0) or 128-byte
+// lines of the resident layout (2^line_log2 records each).
+static dart_status count_marked(const dart_stack *s, const dart_view *v, int line_log2,
+                                uint64_t *out, void *hip_stream) {
+    if (!out) return fail(DART_E_INVAL, "output pointer is NULL");
     RayView rv;
     dart_status st = resolve_view(s, v, &rv);
     if (st != DART_OK) return st;
     hipStream_t stream = (hipStream_t)hip_stream;
-    const uint64_t bits = (uint64_t)s->dev.n[0] * s->dev.n[1] * s->dev.n[2] * s->dev.n_epochs;
+    const uint64_t bits =
+        line_log2 < 0 ? (uint64_t)s->dev.n[0] * s->dev.n[1] * s->dev.n[2] * s->dev.n_epochs
+                      : ((s->dev.epoch_stride * s->dev.n_epochs) >> line_log2) + 1;
     const uint64_t words = (bits + 31) / 32;
     const uint64_t u64s = (words + 1) / 2 + 1;
     unsigned long long *bm = nullptr;
     HIP_TRY(hipMalloc(&bm, u64s * 8), "hipMalloc(bitmap)");
     unsigned long long *cnt = bm + (u64s - 1);
     hipError_t e = launch_fill_u64(bm, u64s, 0ull, stream);
-    if (e == hipSuccess) e = launch_mark(rv, (uint32_t *)bm, stream);
+    if (e == hipSuccess) e = launch_mark(rv, (uint32_t *)bm, line_log2, stream);
     if (e == hipSuccess) e = launch_popcount((const uint32_t *)bm, words, cnt, stream);
     unsigned long long c = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&c, cnt, sizeof(c), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     (void)hipFree(bm);
     if (e != hipSuccess) return hip_fail(e, "count samples");
-    *samples_out = c;
+    *out = c;
     return DART_OK;
+}
+
+extern "C" dart_status dart_count_samples(const dart_stack *s, const dart_view *v,
+                                          uint64_t *samples_out, void *hip_stream) {
+    return count_marked(s, v, -1, samples_out, hip_stream);
+}
+
+extern "C" dart_status dart_count_lines(const dart_stack *s, const dart_view *v,
+                                        uint64_t *lines_out, void *hip_stream) {
+    if (!s) return fail(DART_E_INVAL, "NULL stack");
+    const uint32_t rb = record_bytes(s->dev.store);
+    int line_log2 = 0;
+    while ((rb << (line_log2 + 1)) <= 128u) line_log2++;
+    return count_marked(s, v, line_log2, lines_out, hip_stream);
 }
 
 extern "C" dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t bytes,

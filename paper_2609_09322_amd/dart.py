@@ -31,7 +31,7 @@ DART_ACCUMULATE = 0x80
 
 EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "dart_free_epochs",
            "dart_stack_get_info", "dart_stack_rebrick", "dart_stack_set_placement", "dart_render", "dart_render_batch",
-           "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples",
+           "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples", "dart_count_lines",
            "dart_record_bytes", "dart_bandwidth_probe", "dart_server_create", "dart_submit",
            "dart_poll", "dart_wait", "dart_server_destroy", "dart_server_get_stats",
            "dart_last_error", "dart_version"]
@@ -60,7 +60,7 @@ class dart_stack_info(ctypes.Structure):
 class dart_tuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("orient", ctypes.c_int32)]
+                ("orient", ctypes.c_int32), ("depth_sync", ctypes.c_int32)]
 
 
 class dart_server_stats(ctypes.Structure):
@@ -114,6 +114,7 @@ def _load():
         "dart_set_tuning": [_P],
         "dart_get_tuning": [_P],
         "dart_count_samples": [_P, _P, _P, _P],
+        "dart_count_lines": [_P, _P, _P, _P],
         "dart_record_bytes": [_P, _P],
         "dart_bandwidth_probe": [_P, _P, U64, I32, _P],
         "dart_server_create": [ctypes.c_size_t, I32, I32, _P],
@@ -311,8 +312,8 @@ def dart_autotune(stacks, views, rebrick=False, stream=None):
     return best, ms.value
 
 
-def dart_set_tuning(tile_w, tile_h, waves_per_cu, order=0, orient=1):
-    t = dart_tuning(tile_w, tile_h, waves_per_cu, order, orient)
+def dart_set_tuning(tile_w, tile_h, waves_per_cu, order=0, orient=1, depth_sync=0):
+    t = dart_tuning(tile_w, tile_h, waves_per_cu, order, orient, depth_sync)
     _check(_load().dart_set_tuning(ctypes.byref(t)))
 
 
@@ -326,6 +327,13 @@ def dart_count_samples(stack: Stack, view: View, stream=None) -> int:
     n = ctypes.c_uint64(0)
     _check(_load().dart_count_samples(stack.handle, ctypes.byref(view.c()), ctypes.byref(n),
                                       _stream(stream)))
+    return n.value
+
+
+def dart_count_lines(stack: Stack, view: View, stream=None) -> int:
+    n = ctypes.c_uint64(0)
+    _check(_load().dart_count_lines(stack.handle, ctypes.byref(view.c()), ctypes.byref(n),
+                                    _stream(stream)))
     return n.value
 
 

@@ -116,10 +116,23 @@ def test_random_grids_all_storage(dart, store, flags):
 
 
 @pytest.mark.parametrize("store", ["f32", "f16"])
-def test_batch_equals_plain_and_oracle(dart, store):
+@pytest.mark.parametrize("sync", [0, 1, 3])
+def test_batch_equals_plain_and_oracle(dart, store, sync):
     """The persistent batched kernel gives the same pixels as the plain kernel
-    and as the oracle, with images of ragged sizes and mixed stacks."""
+    and as the oracle, with images of ragged sizes and mixed stacks; also with
+    depth-synchronous marching (sync > 0), which changes only the order in
+    which a wavefront's rays take their cells."""
     import torch
+    saved = dart.dart_get_tuning()
+    dart.dart_set_tuning(32, 2, 8, 0, 1, sync)
+    try:
+        _batch_equals_plain_and_oracle(dart, store, torch)
+    finally:
+        dart.dart_set_tuning(saved.tile_w, saved.tile_h, saved.waves_per_cu, saved.order,
+                             saved.orient, saved.depth_sync)
+
+
+def _batch_equals_plain_and_oracle(dart, store, torch):
     dims_a, dims_b = (24, 20, 28), (16, 16, 16)
     ja, ba, ta = synth.random_stack(dims_a, 5, seed=1, beta_max=0.8)
     jb, bb, tb = synth.random_stack(dims_b, 3, seed=2, beta_max=0.8)
@@ -185,6 +198,24 @@ def test_count_samples_matches_oracle(dart):
         v = dart.View(th, ph, 40, 36, ps, float(t.mean()), 0.7)
         got = dart.dart_count_samples(s, v)
         want = oracle.count_samples(oracle.Stack(j, b, t), oracle.View(th, ph, 40, 36, ps, float(t.mean()), 0.7, 0))
+        assert abs(got - want) <= max(2, 1e-4 * want), (got, want)
+
+
+@pytest.mark.parametrize("store,brick", [("f32", (1, 8, 1)), ("f32", (2, 2, 2)), ("f16", (4, 2, 2)),
+                                         ("bf16", (1, 1, 16))])
+def test_count_lines_matches_oracle_blocks(dart, store, brick):
+    """With a brick of exactly one 128-byte line of records, the distinct lines
+    a view reads are the distinct (brick, epoch) pairs the oracle counts from
+    the geometry alone."""
+    dims = (16, 16, 32)
+    j, b, t = synth.random_stack(dims, 5, seed=19, beta_max=0.5, dtype=np.float32)
+    s = dart.dart_load_epochs(dims, (1, 1, 1), t, j, b, _store(dart, store))
+    dart.dart_stack_rebrick(s, brick)
+    for th, ph, ps in [(40.0, 30.0, 0.7), (90.0, 0.0, 1.3), (120.0, 200.0, 2.6)]:
+        v = dart.View(th, ph, 48, 40, ps, float(t.mean()), 0.7)
+        got = dart.dart_count_lines(s, v)
+        want = oracle.count_blocks(dims, t, oracle.View(th, ph, 48, 40, ps, float(t.mean()), 0.7, 0),
+                                   brick)
         assert abs(got - want) <= max(2, 1e-4 * want), (got, want)
 
 
