@@ -262,6 +262,21 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
         res["plain"] = {"ms_per_step": pms, "images_per_s": n_img / (pms * 1e-3),
                         "cell_steps_per_s": cell_steps / (pms * 1e-3),
                         "identical_to_batched": bool(same)}
+        # the same batched call handing back pinned host images (the render
+        # waits for its device-to-host copies): the PCIe-inclusive rate
+        host_imgs = [torch.empty((v.height, v.width), dtype=torch.float32, pin_memory=True)
+                     for v in views]
+
+        def to_host():
+            dart.dart_render_batch([st] * n_img, views, host_imgs,
+                                   stream=stream, stats=False)
+
+        hwall, _ = time_steps(torch, stream, to_host, max(1, args.steps // 2), 1)
+        hms = 1e3 * hwall / max(1, args.steps // 2)
+        res["host_images"] = {"ms_per_step": hms, "images_per_s": n_img / (hms * 1e-3),
+                              "note": "batched render into pinned host images, "
+                                      "device-to-host copies included"}
+        log(f"host images: {hms:.3f} ms/step")
 
     # accuracy on sampled pixels against the FP64 oracle (dequantised inputs)
     if args.check and host is not None:
@@ -278,11 +293,12 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
 
     cpu = None
     if not args.no_cpu_baseline and host is not None:
-        threads = os.cpu_count() or 1
+        # the host cores this process may use (OMP_NUM_THREADS caps it where set)
+        threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS") or 1 << 10))
         # calibrate on a sample of ~1 s, then size the timed sample for ~15 s
         cal = 8192 * max(1, 16 // n_img) * n_img
         _, n0, s0 = oracle_sample(host, times, views, cal, 11, threads, dtype_name)
-        rays = int(min(1 << 23, max(cal, cal * 15.0 / max(s0, 1e-3))))
+        rays = int(min(1 << 25, max(cal, cal * 15.0 / max(s0, 1e-3))))
         _, n1, s1 = oracle_sample(host, times, views, rays, 12, threads, dtype_name)
         cpu = {"value": n1 / s1, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{rays} random pixels over the {n_img} views ({n1} cell-steps, {s1:.1f} s)",
@@ -324,6 +340,8 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
         "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
         "roofline": roof, "cpu_baseline": cpu,
     }
+    if "host_images" in res:
+        line["host_images"] = res["host_images"]
     if "plain" in res:
         line["plain"] = res["plain"]
         line["speedup_images_per_s_vs_plain"] = line["images_per_s"] / res["plain"]["images_per_s"]

@@ -652,6 +652,21 @@ dart_tuning dart::tuning_for(const dart_stack *s) {
 // ------------------------------------------------------------------ batch planner
 
 // Estimated cell-steps of the ray through the tile centre, times 64 rays.
+// Orientation of a view's tiles (tuning.orient): the tile's long side follows
+// the image-plane projection of the bricks' long axis, so that the lanes of one
+// wave read neighbouring cells of the same cache lines.  True when that turns
+// the tile (tile_w and tile_h swap) for this view.
+static bool orient_flips(const RayView &rv, const dart_tuning &tun) {
+    if (!tun.orient) return false;
+    int a = 0;
+    for (int k = 1; k < 3; k++)
+        if (rv.st.lb[k] > rv.st.lb[a]) a = k;
+    const bool elongated = rv.st.lb[a] > std::min(rv.st.lb[0], std::min(rv.st.lb[1], rv.st.lb[2]));
+    const bool long_u = tun.tile_w >= tun.tile_h;
+    const bool axis_u = fabs(rv.eu[a]) >= fabs(rv.ev[a]);
+    return elongated && long_u != axis_u;
+}
+
 static double tile_cost(const RayView &rv, int tx, int ty, int tw, int th) {
     const double u = ((tx + 0.5) * tw - 0.5 * rv.width) * rv.ps;
     const double w = ((ty + 0.5) * th - 0.5 * rv.height) * rv.ps;
@@ -697,19 +712,7 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         }
         Group &g = groups[it->second];
         const uint32_t vi = (uint32_t)g.views.size();
-        // Orientation of the tile: its long side follows the image-plane
-        // projection of the bricks' long axis, so that the lanes of one wave
-        // read neighbouring cells of the same cache lines.
-        int lw = lw0;
-        if (tun.orient) {
-            int a = 0;
-            for (int k = 1; k < 3; k++)
-                if (rv.st.lb[k] > rv.st.lb[a]) a = k;
-            const bool elongated = rv.st.lb[a] > std::min(rv.st.lb[0], std::min(rv.st.lb[1], rv.st.lb[2]));
-            const bool long_u = tun.tile_w >= tun.tile_h;
-            const bool axis_u = fabs(rv.eu[a]) >= fabs(rv.ev[a]);
-            if (elongated && long_u != axis_u) lw = 6 - lw0;
-        }
+        const int lw = orient_flips(rv, tun) ? 6 - lw0 : lw0;
         rv.tile_w_log2 = lw;
         rv.sync_gap = tun.depth_sync > 0
                           ? tun.depth_sync * std::max(rv.st.cell[0], std::max(rv.st.cell[1], rv.st.cell[2]))
@@ -1078,10 +1081,24 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         }
         if (result == DART_OK) result = rebrick_all(bricks[pick(brick_ms)]);
     }
-    // Stage 2: launch shapes on the chosen layout.
+    // Stage 2: launch shapes on the chosen layout.  A candidate with orient = 1
+    // that turns no view's tiles is the same launch as its orient = 0 twin and
+    // is not timed again (timing noise would otherwise pick between the two).
     if (result == DART_OK) {
+        std::vector<RayView> rvs(n);
+        for (int32_t i = 0; i < n && result == DART_OK; i++)
+            result = resolve_view(stacks[i], &vv[i], &rvs[i]);
+        std::vector<dart_tuning> kept;
+        for (const dart_tuning &c : cands) {
+            bool turns = false;
+            for (int32_t i = 0; i < n; i++) turns |= orient_flips(rvs[i], c);
+            if (c.orient && !turns) continue;
+            kept.push_back(c);
+        }
+        cands.swap(kept);
         std::vector<float> cand_ms;
         for (const dart_tuning &c : cands) {
+            if (result != DART_OK) break;
             float ms = 0;
             result = measure(c, &ms);
             if (result != DART_OK) break;
