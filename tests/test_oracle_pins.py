@@ -482,6 +482,61 @@ def test_p12_penrose_terrell(orc, ejecta_c):
     assert _axis_ratio(img0, v0, 0.0, 99) == pytest.approx(want, abs=0.04)
 
 
+def _moments(img, v):
+    """(second-moment width along e_v, along e_u) of an image."""
+    rows = (np.arange(img.shape[0]) + 0.5 - img.shape[0] / 2) * v.pixel_scale
+    cols = (np.arange(img.shape[1]) + 0.5 - img.shape[1] / 2) * v.pixel_scale
+    V, U = np.meshgrid(rows, cols, indexing="ij")
+    m = img.sum()
+    cv, cu = (img * V).sum() / m, (img * U).sum() / m
+    return (math.sqrt((img * (V - cv) ** 2).sum() / m), math.sqrt((img * (U - cu) ** 2).sum() / m))
+
+
+def _row_peaks(img, rel=0.05):
+    p = img.sum(axis=1)
+    top = p.max()
+    return [i for i in range(1, len(p) - 1) if p[i] > p[i - 1] and p[i] >= p[i + 1] and p[i] > rel * top]
+
+
+def alias_case(orc, dt):
+    """The advancing ejectum alone (Sec. 6.1's setting), epochs every dt,
+    imaged with lookback and no beaming at theta = 45 deg."""
+    times = np.arange(-12.0, 48.0 + 1e-9, dt)
+    j, b, t = synth.twin_ejecta(dims=EJ["dims"], radius=EJ["radius"], gamma=EJ["gamma"],
+                                times=times, t_centre=0.0, sub=4, axis_sep=EJ["axis_sep"])
+    j[:, : EJ["dims"][2] // 2] = 0.0
+    v = orc.View(45.0, 0.0, 200, 200, 0.3, 0.0, 0.6, orc.NO_BEAMING)
+    return j, b, t, v
+
+
+@pytest.mark.parametrize("dt", [8.0, 4.0, 2.0, 0.5])
+def test_p14_aliasing_scale(orc, dt):
+    """Sec. 6.1, Eqs. 24-25: with a cadence dt the image cannot resolve scales
+    below R_crit = v_T dt.  Linear interpolation between snapshots whose
+    observed positions are R_crit apart superposes two copies with weights
+    1 - W and W, W spread uniformly over the image, which adds R_crit^2 / 6 to
+    the variance along the apparent motion (e_v) and nothing across it.  So:
+    several images (aliasing) when R_crit exceeds the diameter, one when it is
+    below the radius, the excess variance within 15% of R_crit^2 / 6, and the
+    image a circle (Penrose-Terrell) once R_crit << R."""
+    j, b, t, v = alias_case(orc, dt)
+    img, _ = orc.render(_stack(orc, j, b, t), v)
+    r_crit = orc.alias_r_crit(math.sqrt(0.75), math.pi / 4, dt)
+    R = EJ["radius"]
+    assert orc.alias_dt_crit(math.sqrt(0.75), math.pi / 4, r_crit) == pytest.approx(dt, rel=1e-12)
+    sv, su = _moments(img, v)
+    peaks = _row_peaks(img)
+    if r_crit > 2 * R:
+        assert len(peaks) >= 3
+    if r_crit < R:
+        assert len(peaks) == 1
+    if r_crit >= 0.5 * R:
+        # the voxelised sphere's own excess (sv^2 - su^2 at dt -> 0) is ~0.1
+        assert sv ** 2 - su ** 2 == pytest.approx(r_crit ** 2 / 6, rel=0.15)
+    else:
+        assert sv / su == pytest.approx(1.0, abs=0.03)
+
+
 # ---------------------------------------------------------------- P13 linearity, symmetry
 
 def test_p13_linearity(orc):
