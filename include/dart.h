@@ -141,6 +141,23 @@ dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info *info);
  * Defaults: origin 0, centre = the grid's own centre.  Finite values only. */
 dart_status dart_stack_set_placement(dart_stack *s, const double origin[3], const double centre[3]);
 
+/* Labelled mode (Sec. 4; partial renders of sub-regions, Sec. 6.2): one stack
+ * made of non-overlapping sub-domains, each a stack with its own dims and cell
+ * size, placed in the domain with dart_stack_set_placement (all with the same
+ * domain centre), and all with the same storage type, device and epoch times.
+ * A render of it (dart_render, dart_render_batch, dart_submit) marches every
+ * ray through each sub-domain in order and sums them in one pass.  The
+ * sub-domains stay owned by the caller; while a labelled stack holds them they
+ * cannot be freed, re-laid or re-placed (DART_E_BUSY), but their epochs may be
+ * refilled with dart_stack_set_epochs.  Overlapping sub-domains would be
+ * counted twice: the caller keeps them disjoint (the leaf blocks of a
+ * refinement hierarchy).  Free it with dart_free_epochs.  dart_stack_get_info
+ * reports the first sub-domain's dims and brick and the bytes of all of them;
+ * dart_stack_rebrick, dart_stack_set_epochs, dart_stack_set_placement,
+ * dart_count_samples, dart_count_lines and dart_autotune with rebrick != 0
+ * return DART_E_INVAL for it.  n_blocks in [1, 65536]; on error *out = NULL. */
+dart_status dart_labelled_create(dart_stack *const *blocks, int32_t n_blocks, dart_stack **out);
+
 /* Re-lays the resident stack with a new brick shape (powers of two, each
  * 1..16, at most 4096 cells per brick); the current shape returns at once.
  * Uses a second copy of the stack when device memory allows, else (when the

@@ -56,7 +56,9 @@ def build(force: bool = True) -> str:
 class _Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("cell", ctypes.c_double * 3),
                 ("n_epochs", ctypes.c_int), ("times", ctypes.POINTER(ctypes.c_double)),
-                ("dtype", ctypes.c_int), ("j", ctypes.c_void_p), ("beta", ctypes.c_void_p)]
+                ("dtype", ctypes.c_int), ("j", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+                ("placed", ctypes.c_int), ("origin", ctypes.c_double * 3),
+                ("centre", ctypes.c_double * 3)]
 
 
 class _View(ctypes.Structure):
@@ -117,12 +119,18 @@ class Stack:
     Arrays may be float64, float32, float16, or uint16 holding bfloat16 bit
     patterns (encoding="bf16"); float32 arrays with encoding "f32_as_bf16" or
     "f32_as_f16" are rounded to that 16-bit type value by value as they are
-    read.  The oracle widens every value to FP64 itself."""
+    read.  The oracle widens every value to FP64 itself.
+
+    origin / centre place the grid inside a larger domain (a sub-domain of the
+    labelled mode, Sec. 4): its lower corner at `origin`, cameras centred on
+    the domain point `centre`.  Both or neither."""
     j: np.ndarray
     beta: np.ndarray
     times: np.ndarray
     cell: tuple = (1.0, 1.0, 1.0)
     encoding: str = None
+    origin: tuple = None
+    centre: tuple = None
 
     def __post_init__(self):
         if self.encoding is None:
@@ -136,6 +144,7 @@ class Stack:
         M, nz, ny, nx = self.j.shape
         assert self.beta.shape == (M, nz, ny, nx, 3)
         assert self.times.shape == (M,)
+        assert (self.origin is None) == (self.centre is None), "give origin and centre together"
 
     @property
     def dims(self):
@@ -152,6 +161,10 @@ class Stack:
         g.dtype = _DT_CODE[self.encoding]
         g.j = self.j.ctypes.data
         g.beta = self.beta.ctypes.data
+        if self.origin is not None:
+            g.placed = 1
+            g.origin[:] = [float(c) for c in self.origin]
+            g.centre[:] = [float(c) for c in self.centre]
         return g
 
 
@@ -201,6 +214,19 @@ def render(stack: Stack, view: View, pixels=None, threads=None):
     """O1.  Returns (intensity, cell_steps).  ``pixels`` is an (n, 2) array of
     (i, j) pixel indices; without it the whole [height][width] image is made."""
     return _run("orc_render", stack, view, pixels, threads)
+
+
+def render_labelled(blocks, view: View, pixels=None, threads=None):
+    """The labelled mode (Sec. 4): a domain given as non-overlapping placed
+    sub-domains, each at its own resolution.  Its image is the sum of the
+    blocks' images (optically thin emission adds along a ray), in block
+    order.  Returns (intensity, cell_steps)."""
+    total, steps = None, 0
+    for b in blocks:
+        img, n = render(b, view, pixels, threads)
+        total = img if total is None else total + img
+        steps += n
+    return total, steps
 
 
 def render_brute(stack: Stack, view: View, pixels=None, threads=None):

@@ -32,6 +32,13 @@
  * entries bound the per-cell chords.  This is deliberately not a DDA.
  * Brute force (O2): the ray is intersected with every cell box of the grid.
  *
+ * Sub-domains (the labelled mode of Sec. 4): a grid may be placed inside a
+ * larger domain (placed = 1): its lower corner sits at `origin` and the camera
+ * is centred on the domain point `centre`, through which the s = 0 plane of
+ * the retarded time also passes.  Everything else is computed in the grid's
+ * own coordinates.  A render of the domain is the sum of the renders of its
+ * non-overlapping sub-domains (optically thin emission adds along the ray).
+ *
  * Flags: ORC_NO_LOOKBACK (tbar = t_obs for every cell, Eq. 3 / Eq. 10),
  * ORC_NO_BEAMING (D = 1), ORC_NEAREST (weight 1 on the epoch closest to tbar,
  * ties to the earlier epoch).
@@ -61,6 +68,9 @@ typedef struct {
     int dtype;            /* ORC_DT_F64 or ORC_DT_F32 for the two arrays below */
     const void *j;        /* [M][nz][ny][nx] rest-frame emissivity */
     const void *beta;     /* [M][nz][ny][nx][3] velocity / c */
+    int placed;           /* 0: the grid is the whole domain */
+    double origin[3];     /* placed: position of the grid's lower corner in the domain */
+    double centre[3];     /* placed: the domain point the camera is centred on */
 } orc_grid;
 
 typedef struct {
@@ -151,7 +161,8 @@ void orc_camera_basis(const orc_grid *g, const orc_view *v, double *out12) {
     for (int a = 0; a < 3; a++) out12[a] = -nhat[a];
     out12[3] = -sp; out12[4] = cp; out12[5] = 0.0;
     out12[6] = -ct * cp; out12[7] = -ct * sp; out12[8] = st;
-    for (int a = 0; a < 3; a++) out12[9 + a] = 0.5 * g->n[a] * g->cell[a];
+    for (int a = 0; a < 3; a++)
+        out12[9 + a] = g->placed ? g->centre[a] - g->origin[a] : 0.5 * g->n[a] * g->cell[a];
 }
 
 static void make_camera(const orc_grid *g, const orc_view *v, orc_camera *cam) {

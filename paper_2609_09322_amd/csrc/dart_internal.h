@@ -33,10 +33,19 @@ struct StackDev {
     double cell[3];
 };
 
+// One sub-domain of a labelled stack: its grid and the camera centre in the
+// grid's own coordinates (the domain centre minus the grid's origin).
+struct Block {
+    StackDev st;
+    double centre[3];
+};
+
 // One view, resolved on the host in FP64.
 struct RayView {
     double shat[3], eu[3], ev[3], centre[3];
     double inv_shat[3];     // 1 / s_hat per axis (0 where s_hat has a zero component)
+    float shat_hi[3];       // s_hat rounded to FP32, and the rest: s_hat = hi + lo to
+    float shat_lo[3];       // ~2^-48, for the FP32 Doppler of 16-bit stacks
     double ps;              // pixel scale
     double t_obs;
     double s_lo, s_hi;      // temporal window expressed in s: [t_obs - t_{M-1}, t_obs - t_0]
@@ -50,7 +59,9 @@ struct RayView {
     int32_t out_f64;
     int32_t acc_index;      // slot in the flux / step accumulators
     int32_t tile_w_log2;    // batched kernel: tile width 1 << tile_w_log2, height 64 >> it
-    StackDev st;
+    StackDev st;            // the stack (a labelled stack: its first sub-domain)
+    const Block *blocks;    // labelled stack: its sub-domains (device), else null
+    int32_t n_blocks;       // 0 for a plain stack
 };
 
 struct Tile {

@@ -76,7 +76,10 @@ __device__ __forceinline__ void decode(const typename RecT<S>::raw &r, V &j, V &
 // D^p j of one record (Eq. 14 raised to p, times the rest-frame emissivity).
 // FP64 stacks: all in FP64.  FP32 stacks: 1 - beta^2 and 1 + beta.s in FP64
 // (the two quantities that cancel at high Lorentz factor), logs in FP32.
-// 16-bit stacks: FP32 FMA chains starting from 1.
+// 16-bit stacks: FP32 FMA chains starting from 1, with s_hat split in two
+// floats: rounding s_hat to FP32 alone moves 1 + beta.s by ~6e-8 absolute,
+// which near the beaming peak (1 + beta.s ~ 0.05 at Lorentz factor 4) is a
+// systematic ~1e-6 relative error of D^p over the whole image.
 template <int S>
 __device__ __forceinline__ typename RecT<S>::val boosted(const typename RecT<S>::raw &r,
                                                         const RayView &v, bool beaming) {
@@ -97,7 +100,8 @@ __device__ __forceinline__ typename RecT<S>::val boosted(const typename RecT<S>:
         return j * __builtin_amdgcn_exp2f(e);
     } else {
         float q = fmaf(-bx, bx, fmaf(-by, by, fmaf(-bz, bz, 1.0f)));
-        float rr = fmaf(bx, (float)v.shat[0], fmaf(by, (float)v.shat[1], fmaf(bz, (float)v.shat[2], 1.0f)));
+        float rr = fmaf(bx, v.shat_hi[0], fmaf(by, v.shat_hi[1], fmaf(bz, v.shat_hi[2], 1.0f)));
+        rr += fmaf(bx, v.shat_lo[0], fmaf(by, v.shat_lo[1], bz * v.shat_lo[2]));
         float p = (float)v.p;
         float e = fmaf(0.5f * p, __builtin_amdgcn_logf(q), -p * __builtin_amdgcn_logf(rr));
         return j * __builtin_amdgcn_exp2f(e);
@@ -124,13 +128,13 @@ struct Ray {
 // FP64 set-up of pixel (pi, pj): slab test, clip to the window, starting cell
 // and crossing sequences.  False when no cell of the ray can contribute.
 template <typename R>
-__device__ __forceinline__ bool ray_setup(const RayView &v, int pi, int pj, Ray<R> &r) {
-    const StackDev &st = v.st;
+__device__ __forceinline__ bool ray_setup(const RayView &v, const StackDev &st,
+                                          const double *centre, int pi, int pj, Ray<R> &r) {
     const double u = (pi + 0.5 - 0.5 * v.width) * v.ps;
     const double w = (pj + 0.5 - 0.5 * v.height) * v.ps;
     double o[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) o[a] = v.centre[a] + u * v.eu[a] + w * v.ev[a];
+    for (int a = 0; a < 3; a++) o[a] = centre[a] + u * v.eu[a] + w * v.ev[a];
     double s_in = -INFINITY, s_out = INFINITY;
     bool hit = true;
 #pragma unroll
@@ -218,8 +222,8 @@ struct Bracket {
 typedef const double __attribute__((address_space(1))) gdouble;
 
 template <typename R>
-__device__ __forceinline__ void bracket_init(const RayView &v, bool lookback, Bracket<R> &b) {
-    const StackDev &st = v.st;
+__device__ __forceinline__ void bracket_init(const RayView &v, const StackDev &st, bool lookback,
+                                             Bracket<R> &b) {
     gdouble *t = (gdouble *)st.times, *idt = (gdouble *)st.inv_dt;
     const int M = st.n_epochs;
     b.m = lookback ? (M >= 2 ? M - 2 : 0) : v.fixed_m;
@@ -229,8 +233,9 @@ __device__ __forceinline__ void bracket_init(const RayView &v, bool lookback, Br
 }
 
 template <typename R>
-__device__ __forceinline__ void bracket_seek(const RayView &v, R mid, Bracket<R> &b) {
-    gdouble *t = (gdouble *)v.st.times, *idt = (gdouble *)v.st.inv_dt;
+__device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &st, R mid,
+                                             Bracket<R> &b) {
+    gdouble *t = (gdouble *)st.times, *idt = (gdouble *)st.inv_dt;
     while (b.m > 0 && mid > b.am) {
         b.m--;
         b.am1 = b.am;
@@ -248,13 +253,13 @@ template <typename R>
 __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint32_t *bitmap,
                                          int line_log2) {
     Ray<R> r;
-    if (!ray_setup(v, pi, pj, r)) return;
     const StackDev &st = v.st;
+    if (!ray_setup(v, st, v.centre, pi, pj, r)) return;
     const bool lookback = !(v.flags & F_NO_LOOKBACK);
     const bool single = (v.flags & F_NEAREST) || st.n_epochs == 1;
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
     Bracket<R> br;
-    bracket_init(v, lookback, br);
+    bracket_init(v, st, lookback, br);
     const uint64_t ncell = (uint64_t)st.n[0] * st.n[1] * st.n[2];
     for (int guard = st.n[0] + st.n[1] + st.n[2] + 3; guard > 0; guard--) {
         const R entry = fmax(r.sb0, fmax(r.sb1, r.sb2));
@@ -264,7 +269,7 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
         if (ds > (R)0 && mid >= r_lo && mid <= r_hi) {
             R wt = (R)v.fixed_w;
             if (lookback) {
-                bracket_seek(v, mid, br);
+                bracket_seek(v, st, mid, br);
                 wt = (br.am - mid) * br.inv_dt;
             }
             int m0 = br.m;
@@ -324,16 +329,16 @@ __device__ __forceinline__ R wave_min(R x) {
 //      until all rays of the wavefront have ended, including lanes whose ray
 //      misses the grid.
 template <int S, typename R, int SYNC>
-__device__ __forceinline__ double march(const RayView &v, int pi, int pj, bool in_image,
+__device__ __forceinline__ double march(const RayView &v, const StackDev &st,
+                                        const double *centre, int pi, int pj, bool in_image,
                                         uint32_t &nsteps) {
     using A = typename std::conditional<S == ST_F64, double, float>::type;
     using Raw = typename RecT<S>::raw;
     using GRaw = const Raw __attribute__((address_space(1)));
     constexpr int K = CELLS_PER_BATCH;
     Ray<R> r;
-    bool alive = in_image && ray_setup(v, pi, pj, r);
+    bool alive = in_image && ray_setup(v, st, centre, pi, pj, r);
     if (SYNC == 0 && !alive) return 0.0;
-    const StackDev &st = v.st;
     const bool lookback = !(v.flags & F_NO_LOOKBACK);
     const bool beaming = !(v.flags & F_NO_BEAMING);
     const int M = st.n_epochs;
@@ -347,7 +352,7 @@ __device__ __forceinline__ double march(const RayView &v, int pi, int pj, bool i
     // only one epoch is used
     const uint64_t second = single ? 0 : estride;
     Bracket<R> br;
-    bracket_init(v, lookback, br);
+    bracket_init(v, st, lookback, br);
     GRaw *ebase = gdata + (uint64_t)br.m * estride;  // records of epoch br.m
     int ebase_m = br.m;
     A sum = 0, comp = 0;
@@ -382,7 +387,7 @@ __device__ __forceinline__ double march(const RayView &v, int pi, int pj, bool i
                     const bool contrib = ds > (R)0 && mid >= r_lo && mid <= r_hi;
                     R wt = (R)v.fixed_w;
                     if (lookback) {
-                        bracket_seek(v, mid, br);
+                        bracket_seek(v, st, mid, br);
                         wt = (br.am - mid) * br.inv_dt;
                     }
                     if (br.m != ebase_m) {
@@ -439,6 +444,23 @@ __device__ __forceinline__ double march(const RayView &v, int pi, int pj, bool i
     return (double)sum - (double)comp;
 }
 
+// Intensity of pixel (pi, pj): one march through the stack, or, for a labelled
+// stack, one march through each of its sub-domains in order, summed (emission
+// adds along the ray; sub-domains do not overlap).  The block loop is uniform
+// over the wavefront, as the depth-synchronous mode needs.
+template <int S, typename R, int SYNC>
+__device__ __forceinline__ double pixel_value(const RayView &v, int pi, int pj, bool in_image,
+                                              uint32_t &nsteps) {
+    const int nb = v.n_blocks > 0 ? v.n_blocks : 1;
+    double acc = 0.0;
+    for (int b = 0; b < nb; b++) {
+        const StackDev &st = v.n_blocks > 0 ? v.blocks[b].st : v.st;
+        const double *centre = v.n_blocks > 0 ? v.blocks[b].centre : v.centre;
+        acc += march<S, R, SYNC>(v, st, centre, pi, pj, in_image, nsteps);
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------------ reductions
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -476,7 +498,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
     uint32_t ns = 0;
     if (idx < npix) {
         const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
-        val = march<S, R, 0>(v, pi, pj, true, ns);
+        val = pixel_value<S, R, 0>(v, pi, pj, true, ns);
         store_pixel(v, pi, pj, val);
     }
     const double fs = wave_sum(val);
@@ -518,7 +540,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
                        (lane >> tw_log2);
         uint32_t ns = 0;
         const bool in_image = pi < v.width && pj < v.height;
-        const double val = march<S, R, SYNC>(v, pi, pj, in_image, ns);
+        const double val = pixel_value<S, R, SYNC>(v, pi, pj, in_image, ns);
         if (in_image) store_pixel(v, pi, pj, val);
         const double fs = wave_sum(val);
         const uint32_t cs = wave_sum_u32(ns);

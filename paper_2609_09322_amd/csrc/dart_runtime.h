@@ -26,6 +26,13 @@ struct dart_stack {
     std::mutex mu;
     std::vector<std::pair<hipStream_t, hipEvent_t>> uses;  // last render per stream
     std::atomic<int> pinned{0};                            // server requests holding the stack
+    // labelled stack: its sub-domains (owned by the caller) and their device
+    // descriptors; a stack that is a sub-domain counts the labelled stacks
+    // holding it in `refs`
+    std::vector<dart_stack *> parts;
+    dart::Block *dev_blocks = nullptr;
+    std::atomic<int> refs{0};
+    bool labelled() const { return !parts.empty(); }
 };
 
 namespace dart {

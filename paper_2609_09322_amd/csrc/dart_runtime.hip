@@ -185,6 +185,7 @@ static dart_status set_epochs_impl(dart_stack *s, int32_t m0, int32_t count, dar
                                    const void *j, const void *beta, uint32_t flags,
                                    hipStream_t stream) {
     if (!s) return fail(DART_E_INVAL, "stack is NULL");
+    if (s->labelled()) return fail(DART_E_INVAL, "fill the sub-domains of a labelled stack instead");
     if (!j || !beta) return fail(DART_E_INVAL, "emissivity/velocity is NULL");
     if (m0 < 0 || count < 1 || m0 + count > s->dev.n_epochs)
         return fail(DART_E_INVAL, "epoch range [%d, %d) outside [0, %d)", m0, m0 + count,
@@ -302,10 +303,72 @@ bool dart::stack_busy(const dart_stack *cs) {
 extern "C" dart_status dart_free_epochs(dart_stack *s) {
     if (!s) return fail(DART_E_INVAL, "stack is NULL");
     if (stack_busy(s)) return fail(DART_E_BUSY, "renders that read this stack are in flight");
+    if (s->refs.load() > 0)
+        return fail(DART_E_BUSY, "the stack is a sub-domain of %d labelled stack(s)", s->refs.load());
     for (auto &u : s->uses) (void)hipEventDestroy(u.second);
-    (void)hipFree((void *)s->dev.data);
-    (void)hipFree((void *)s->dev.times);
+    if (s->labelled()) {
+        // the grids belong to the sub-domains
+        (void)hipFree(s->dev_blocks);
+        for (dart_stack *p : s->parts) p->refs--;
+    } else {
+        (void)hipFree((void *)s->dev.data);
+        (void)hipFree((void *)s->dev.times);
+    }
     delete s;
+    return DART_OK;
+}
+
+extern "C" dart_status dart_labelled_create(dart_stack *const *blocks, int32_t n_blocks,
+                                            dart_stack **out) {
+    if (out) *out = nullptr;
+    if (!blocks || !out || n_blocks < 1) return fail(DART_E_INVAL, "bad labelled-stack arguments");
+    if (n_blocks > 65536) return fail(DART_E_INVAL, "at most 65536 sub-domains");
+    const dart_stack *b0 = blocks[0];
+    for (int32_t i = 0; i < n_blocks; i++) {
+        const dart_stack *b = blocks[i];
+        if (!b) return fail(DART_E_INVAL, "blocks[%d] is NULL", i);
+        if (b->labelled()) return fail(DART_E_INVAL, "blocks[%d] is itself a labelled stack", i);
+        for (int32_t k = 0; k < i; k++)
+            if (blocks[k] == b) return fail(DART_E_INVAL, "blocks[%d] repeats blocks[%d]", i, k);
+        if (b->storage != b0->storage) return fail(DART_E_INVAL, "blocks[%d]: another storage type", i);
+        if (b->device != b0->device) return fail(DART_E_INVAL, "blocks[%d]: another device", i);
+        if (b->times != b0->times) return fail(DART_E_INVAL, "blocks[%d]: other epoch times", i);
+        for (size_t m = 0; m < b->filled.size(); m++)
+            if (!b->filled[m]) return fail(DART_E_INVAL, "blocks[%d]: epoch %zu never filled", i, m);
+        if (n_blocks > 1 && !b->placed)
+            return fail(DART_E_INVAL, "blocks[%d] is not placed (dart_stack_set_placement)", i);
+        for (int a = 0; a < 3; a++)
+            if (b->placed && b->centre[a] != b0->centre[a])
+                return fail(DART_E_INVAL, "blocks[%d]: another domain centre", i);
+    }
+    std::vector<Block> hb(n_blocks);
+    for (int32_t i = 0; i < n_blocks; i++) {
+        const dart_stack *b = blocks[i];
+        hb[i].st = b->dev;
+        for (int a = 0; a < 3; a++)
+            hb[i].centre[a] = b->placed ? b->centre[a] - b->origin[a] : 0.5 * b->dev.n[a] * b->dev.cell[a];
+    }
+    HIP_TRY(hipSetDevice(b0->device), "hipSetDevice");
+    Block *d = nullptr;
+    HIP_TRY(hipMalloc(&d, hb.size() * sizeof(Block)), "hipMalloc(blocks)");
+    hipError_t e = hipMemcpy(d, hb.data(), hb.size() * sizeof(Block), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "upload blocks");
+    }
+    dart_stack *s = new dart_stack;
+    s->dev = b0->dev;
+    s->storage = b0->storage;
+    s->times = b0->times;
+    s->filled.assign(b0->filled.size(), 1);
+    s->device = b0->device;
+    s->dev_blocks = d;
+    for (int32_t i = 0; i < n_blocks; i++) {
+        s->parts.push_back(blocks[i]);
+        s->bytes += blocks[i]->bytes;
+        blocks[i]->refs++;
+    }
+    *out = s;
     return DART_OK;
 }
 
@@ -330,6 +393,8 @@ extern "C" dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_ou
 extern "C" dart_status dart_stack_set_placement(dart_stack *s, const double origin[3],
                                                 const double centre[3]) {
     if (!s || !origin || !centre) return fail(DART_E_INVAL, "NULL argument");
+    if (s->labelled()) return fail(DART_E_INVAL, "a labelled stack is placed by its sub-domains");
+    if (s->refs.load() > 0) return fail(DART_E_BUSY, "the stack is a sub-domain of a labelled stack");
     for (int a = 0; a < 3; a++)
         if (!isfinite(origin[a]) || !isfinite(centre[a]))
             return fail(DART_E_INVAL, "origin and centre must be finite");
@@ -352,6 +417,8 @@ extern "C" dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3],
         cells *= brick[a];
     }
     if (cells > 4096) return fail(DART_E_INVAL, "brick larger than 4096 cells");
+    if (s->labelled()) return fail(DART_E_INVAL, "re-lay the sub-domains of a labelled stack before joining them");
+    if (s->refs.load() > 0) return fail(DART_E_BUSY, "the stack is a sub-domain of a labelled stack");
     if (stack_busy(s)) return fail(DART_E_BUSY, "renders that read this stack are in flight");
     if (lb[0] == s->dev.lb[0] && lb[1] == s->dev.lb[1] && lb[2] == s->dev.lb[2]) return DART_OK;
     hipStream_t stream = (hipStream_t)hip_stream;
@@ -446,6 +513,7 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     if ((v->flags & DART_ACCUMULATE) && !(v->flags & DART_DEVICE_PTRS))
         return fail(DART_E_INVAL, "DART_ACCUMULATE needs a device image (DART_DEVICE_PTRS)");
     memset(rv, 0, sizeof(*rv));
+    const dart_stack *geo = s->labelled() ? s->parts[0] : s;  // camera centre, tile costs
     double st, ct, sp, cp;
     sincos_deg(v->theta_deg, &st, &ct);
     sincos_deg(v->phi_deg, &sp, &cp);
@@ -453,9 +521,12 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     for (int a = 0; a < 3; a++) {
         rv->shat[a] = -nhat[a];
         rv->inv_shat[a] = rv->shat[a] != 0.0 ? 1.0 / rv->shat[a] : 0.0;
+        rv->shat_hi[a] = (float)rv->shat[a];
+        rv->shat_lo[a] = (float)(rv->shat[a] - (double)rv->shat_hi[a]);
         // kernels work in grid-local coordinates: the camera centre relative
         // to the grid's lower corner
-        rv->centre[a] = s->placed ? s->centre[a] - s->origin[a] : 0.5 * s->dev.n[a] * s->dev.cell[a];
+        rv->centre[a] = geo->placed ? geo->centre[a] - geo->origin[a]
+                                    : 0.5 * geo->dev.n[a] * geo->dev.cell[a];
     }
     rv->eu[0] = -sp; rv->eu[1] = cp; rv->eu[2] = 0.0;
     rv->ev[0] = -ct * cp; rv->ev[1] = -ct * sp; rv->ev[2] = st;
@@ -469,12 +540,16 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     // magnitude ~L/2 carry ~1e-5 absolute rounding, which chords at jumps of
     // the emissivity (a jet surface) turn into ~1e-5 relative pixel errors,
     // the size of the FP32 tolerance.  16-bit stacks keep FP32 crossings.
-    if (s->dev.n[0] + s->dev.n[1] + s->dev.n[2] > 4096 || s->dev.store == ST_F32)
-        rv->flags |= F_F64_DDA;
+    int64_t most_cells = (int64_t)s->dev.n[0] + s->dev.n[1] + s->dev.n[2];
+    for (const dart_stack *p : s->parts)
+        most_cells = std::max(most_cells, (int64_t)p->dev.n[0] + p->dev.n[1] + p->dev.n[2]);
+    if (most_cells > 4096 || s->dev.store == ST_F32) rv->flags |= F_F64_DDA;
     rv->width = v->width;
     rv->height = v->height;
     rv->out_f64 = v->out_dtype == DART_F64;
     rv->st = s->dev;
+    rv->blocks = s->dev_blocks;
+    rv->n_blocks = (int32_t)s->parts.size();
     const std::vector<double> &t = s->times;
     const int M = (int)t.size();
     if (v->flags & DART_NO_LOOKBACK) {
@@ -972,6 +1047,9 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
                                      int32_t rebrick, dart_tuning *best_out, double *best_ms_out,
                                      void *hip_stream) {
     if (n < 1 || !stacks || !views) return fail(DART_E_INVAL, "bad autotune arguments");
+    for (int32_t i = 0; i < n; i++)
+        if (!stacks[i] || (rebrick && stacks[i]->labelled()))
+            return fail(DART_E_INVAL, "stacks[%d]: NULL, or labelled with rebrick != 0", i);
     hipStream_t stream = (hipStream_t)hip_stream;
     // scratch device images
     std::vector<dart_view> vv(views, views + n);
@@ -1152,6 +1230,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
 static dart_status count_marked(const dart_stack *s, const dart_view *v, int line_log2,
                                 uint64_t *out, void *hip_stream) {
     if (!out) return fail(DART_E_INVAL, "output pointer is NULL");
+    if (s && s->labelled()) return fail(DART_E_INVAL, "count the sub-domains of a labelled stack");
     RayView rv;
     dart_status st = resolve_view(s, v, &rv);
     if (st != DART_OK) return st;

@@ -30,7 +30,8 @@ DART_KERNEL_PLAIN = 0x40
 DART_ACCUMULATE = 0x80
 
 EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "dart_free_epochs",
-           "dart_stack_get_info", "dart_stack_rebrick", "dart_stack_set_placement", "dart_render", "dart_render_batch",
+           "dart_stack_get_info", "dart_stack_rebrick", "dart_stack_set_placement",
+           "dart_labelled_create", "dart_render", "dart_render_batch",
            "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples", "dart_count_lines",
            "dart_record_bytes", "dart_bandwidth_probe", "dart_server_create", "dart_submit",
            "dart_poll", "dart_wait", "dart_server_destroy", "dart_server_get_stats",
@@ -108,6 +109,7 @@ def _load():
         "dart_stack_get_info": [_P, _P],
         "dart_stack_rebrick": [_P, _P, _P],
         "dart_stack_set_placement": [_P, _P, _P],
+        "dart_labelled_create": [_P, I32, _P],
         "dart_render": [_P, _P, _P, _P, _P, _P],
         "dart_render_batch": [_P, _P, I32, _P, _P, _P, _P],
         "dart_autotune": [_P, _P, I32, I32, _P, _P, _P],
@@ -256,6 +258,16 @@ def dart_stack_set_placement(stack: Stack, origin, centre):
     o = (ctypes.c_double * 3)(*[float(v) for v in origin])
     c = (ctypes.c_double * 3)(*[float(v) for v in centre])
     _check(_load().dart_stack_set_placement(stack.handle, o, c))
+
+
+def dart_labelled_create(blocks) -> Stack:
+    """A labelled stack over placed sub-domain stacks (which it keeps alive)."""
+    arr = (ctypes.c_void_p * len(blocks))(*[b.handle for b in blocks])
+    out = ctypes.c_void_p()
+    _check(_load().dart_labelled_create(arr, len(blocks), ctypes.byref(out)))
+    s = Stack(out.value)
+    s.parts = list(blocks)
+    return s
 
 
 def dart_record_bytes(stack: Stack) -> int:

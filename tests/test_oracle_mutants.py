@@ -68,8 +68,13 @@ MUTANTS = {
     "eu_flipped": [("out12[3] = -sp; out12[4] = cp;", "out12[3] = sp; out12[4] = -cp;")],
     "nhat_sin_cos_phi_swapped": [("double nhat[3] = {st * cp, st * sp, ct};",
                                   "double nhat[3] = {st * sp, st * cp, ct};")],
-    "centre_off_by_half_cell": [("out12[9 + a] = 0.5 * g->n[a] * g->cell[a];",
-                                 "out12[9 + a] = 0.5 * (g->n[a] + 1) * g->cell[a];")],
+    "centre_off_by_half_cell": [(": 0.5 * g->n[a] * g->cell[a];",
+                                 ": 0.5 * (g->n[a] + 1) * g->cell[a];")],
+    # sub-domains (labelled mode)
+    "placement_origin_sign": [("g->placed ? g->centre[a] - g->origin[a]",
+                               "g->placed ? g->centre[a] + g->origin[a]")],
+    "placement_ignores_centre": [("g->placed ? g->centre[a] - g->origin[a]",
+                                  "g->placed ? 0.5 * g->n[a] * g->cell[a] - g->origin[a]")],
     # 16-bit decoding and round-on-read
     "bf16_decode_shift": [("uint32_t u = (uint32_t)((const uint16_t *)p)[idx] << 16;",
                            "uint32_t u = (uint32_t)((const uint16_t *)p)[idx] << 15;")],
