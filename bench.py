@@ -685,6 +685,113 @@ def render_slabs(args, dart, torch, dims, M, seed, gamma, knots, views, whole_im
             "tolerance": {"flux": 1e-6, "pixel": 1e-5}}
 
 
+def run_labelled_workload(args, dart, torch):
+    """The jet grid (256x256x512, 16 epochs, FP32) in the labelled mode: the
+    jet's core (x, y in [64, 192), z in [171, 341)) refined twice, the rest
+    as six coarse sub-domains around it; the four jet views in one batch."""
+    import synth
+    dims, M = (256, 256, 512), 16
+    t0 = time.time()
+    j, b, times = synth.jet_torch(dims, M, 2, gamma_spine=5.0, n_knots=4)
+    torch.cuda.synchronize()
+    boxes = [((0, 256), (0, 256), (0, 171)), ((0, 256), (0, 256), (341, 512)),
+             ((0, 64), (0, 256), (171, 341)), ((192, 256), (0, 256), (171, 341)),
+             ((64, 192), (0, 64), (171, 341)), ((64, 192), (192, 256), (171, 341))]
+    core = ((64, 192), (64, 192), (171, 341))
+    centre = (128.0, 128.0, 256.0)
+    parts, host = [], []
+
+    def add(jb, bb, cell, org):
+        nz, ny, nx = jb.shape[1:4]
+        s = dart.dart_load_epochs((nx, ny, nz), cell, times, jb, bb, dart.DART_F32)
+        torch.cuda.synchronize()   # the load reads jb, bb in stream order
+        dart.dart_stack_rebrick(s, (1, 8, 1))
+        dart.dart_stack_set_placement(s, org, centre)
+        parts.append(s)
+        if args.check:
+            host.append((jb.cpu().numpy(), bb.cpu().numpy(), cell, org))
+
+    for (x0, x1), (y0, y1), (z0, z1) in boxes:
+        add(j[:, z0:z1, y0:y1, x0:x1].contiguous(), b[:, z0:z1, y0:y1, x0:x1].contiguous(),
+            (1.0, 1.0, 1.0), (x0, y0, z0))
+    (x0, x1), (y0, y1), (z0, z1) = core
+    jc = j[:, z0:z1, y0:y1, x0:x1]
+    bc = b[:, z0:z1, y0:y1, x0:x1]
+    del j, b
+    jr = jc.repeat_interleave(2, dim=1).repeat_interleave(2, dim=2).repeat_interleave(2, dim=3)
+    br = bc.repeat_interleave(2, dim=1).repeat_interleave(2, dim=2).repeat_interleave(2, dim=3)
+    del jc, bc
+    add(jr.contiguous(), br.contiguous(), (0.5, 0.5, 0.5), (x0, y0, z0))
+    del jr, br
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    lab = dart.dart_labelled_create(parts)
+    gb = dart.dart_stack_get_info(lab).device_bytes / 1e9
+    log(f"labelled stack: {len(parts)} sub-domains, {gb:.1f} GB, built in {time.time() - t0:.1f} s")
+    L = synth.diag(dims)
+    views = [dart.View(th, 0.0, 512, 512, L / 512, 0.0, 0.6) for th in (10.0, 30.0, 60.0, 90.0)]
+    stream = torch.cuda.Stream()
+    if args.tuning:
+        f = [int(x) for x in normalise_tuning(args.tuning).split(",")]
+        dart.dart_set_tuning(f[0], f[1], f[2], f[3], f[4], f[8])
+        best = dart.dart_get_tuning()
+    else:
+        best, _ = dart.dart_autotune([lab] * 4, views, rebrick=False, stream=stream)
+    tuning = tuning_dict(best, dart.dart_stack_get_info(parts[0]))
+    imgs = [torch.zeros((512, 512), dtype=torch.float32, device="cuda") for _ in views]
+    flux, steps = dart.dart_render_batch([lab] * 4, views, imgs, stream=stream)
+    cell_steps = int(np.sum(steps))
+
+    def batched():
+        dart.dart_render_batch([lab] * 4, views, imgs, stream=stream, stats=False)
+
+    wall, per = time_steps(torch, stream, batched, args.steps, args.warmup)
+    ms_step = 1e3 * wall / args.steps
+    pl = [torch.zeros_like(im) for im in imgs]
+
+    def plain():
+        for v, im in zip(views, pl):
+            dart.dart_render(lab, v, im, stream=stream, stats=False)
+
+    pwall, _ = time_steps(torch, stream, plain, args.steps, args.warmup)
+    pms = 1e3 * pwall / args.steps
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, c) for a, c in zip(imgs, pl))
+    log(f"labelled: batched {ms_step:.3f} ms/step, plain {pms:.3f} ms/step, {cell_steps:.4e} cell-steps")
+    acc = None
+    if args.check:
+        import oracle
+        oparts = [oracle.Stack(jb, bb, times, cell=cell, origin=org, centre=centre)
+                  for jb, bb, cell, org in host]
+        rng = np.random.default_rng(7)
+        errs = []
+        for k, v in enumerate(views):
+            pix = np.stack([rng.integers(0, 512, 512), rng.integers(0, 512, 512)], axis=1).astype(np.int32)
+            ov = oracle.View(v.theta_deg, v.phi_deg, 512, 512, v.pixel_scale, 0.0, 0.6, 0)
+            ref, _ = oracle.render_labelled(oparts, ov, pixels=pix)
+            got = imgs[k].cpu().numpy()
+            gv = got[pix[:, 1], pix[:, 0]].astype(np.float64)
+            errs.append(float(pix_err(gv, ref, float(np.abs(got).max())).max()))
+        acc = {"max_pixel_rel_err": max(errs), "sampled_pixels": 512 * len(views),
+               "tolerance": 1e-5}
+        log(f"accuracy vs the oracle's labelled render: {acc}")
+    return {
+        "metric": "cell-steps/s & images/s (batched vs plain kernel) at 1e-5 rel; p50/p99 ms",
+        "value": cell_steps / (ms_step * 1e-3), "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "labelled: jet 256x256x512, 16 epochs, FP32, core refined 2x "
+                               "(7 sub-domains), 4 views 512^2", "sub_domains": len(parts),
+                   "resident_gb": gb, "cell_steps_per_step": cell_steps},
+        "images_per_s": 4 / (ms_step * 1e-3), "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
+        "plain": {"ms_per_step": pms, "images_per_s": 4 / (pms * 1e-3),
+                  "identical_to_batched": bool(same)},
+        "speedup_images_per_s_vs_plain": pms / ms_step,
+        "accuracy": acc, "tuning": tuning, "roofline": None, "cpu_baseline": None,
+    }
+
+
 # --------------------------------------------------------------------------- counters
 
 def pmc_summary(fetch_csv, write_csv, workload, tuning):
@@ -725,7 +832,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="jet", choices=["jet", "batch", "serve", "large"])
+    ap.add_argument("--workload", default="jet",
+                    choices=["jet", "batch", "serve", "large", "labelled"])
     ap.add_argument("--large-views", type=int, default=256)
     ap.add_argument("--large-check", type=int, default=4)
     ap.add_argument("--large-slabs", type=int, default=2,
@@ -785,6 +893,8 @@ def main():
             args.storage, check_views=8)
     elif args.workload == "serve":
         line = run_serve_workload(args, dart, torch)
+    elif args.workload == "labelled":
+        line = run_labelled_workload(args, dart, torch)
     else:
         line = run_large_workload(args, dart, torch)
     print(json.dumps(line), flush=True)
