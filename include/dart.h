@@ -207,6 +207,52 @@ dart_status dart_render_batch(const dart_stack *const *stacks, const dart_view *
                               void *const *images, double *flux_out, uint64_t *steps_out,
                               void *hip_stream);
 
+/* ------------------------------------------------------------- streaming --
+ * Out-of-core rendering (Sec. 4, Fig. 5: snapshot by snapshot into one image
+ * buffer per camera; Sec. 5.2 and 6.2: data larger than device memory, and
+ * skipping snapshots no camera needs).  The epochs stay in the caller's memory
+ * and pass through a ring of `ring_epochs` device slots: epoch interval
+ * [t_m, t_{m+1}) is rendered from epochs m and m + 1 alone over the cells whose
+ * retarded time lies in it (the last interval closed) and added into the
+ * images, so the result is the same lookback sum as a resident render (cell
+ * steps identical; pixels differ only by the rounding of the per-interval
+ * partial sums).  Streamed renders use FP64 ray parameters for every storage
+ * type (DART_FORCE_F64_DDA), so a chord midpoint on an interval boundary falls
+ * on the same side in both intervals.  Intervals no view can see are skipped and their epochs never
+ * read.  The next epoch is uploaded and converted on an internal copy stream
+ * while the current interval renders; host sources overlap with rendering only
+ * when they are in pinned memory.
+ *   dims, cell, n_epochs, epoch_times, storage: as for dart_load_epochs.
+ *   ring_epochs: device epoch slots, in [3, 64] (3 is enough for overlap).
+ *   brick: brick shape of the slots (nullable: the default one).
+ * Device memory held: ring_epochs epochs in the storage type, one epoch of
+ * source data (host sources), descriptors and staging for host images. */
+typedef struct dart_streamer dart_streamer;
+typedef struct {
+    int32_t epochs_loaded;   /* epochs the last render call converted into the ring */
+    int32_t epochs_skipped;  /* epochs no needed interval used (never read) */
+    int32_t intervals;       /* epoch intervals the last call rendered */
+    int32_t reserved;
+    uint64_t bytes_uploaded; /* host-to-device source bytes of the last call */
+} dart_stream_stats;
+dart_status dart_streamer_create(const int32_t dims[3], const double cell[3], int32_t n_epochs,
+                                 const double *epoch_times, dart_dtype storage,
+                                 int32_t ring_epochs, const int32_t brick[3], dart_streamer **out);
+/* Renders n views of the epoch series (emissivity [M][nz][ny][nx], velocity
+ * [M][nz][ny][nx][3], src_dtype DART_F32 or DART_F64; src_flags
+ * DART_DEVICE_PTRS when they are device arrays).  Views, images, flux_out and
+ * steps_out as for dart_render_batch (the batched kernel with the current
+ * dart_set_tuning shape); DART_ACCUMULATE adds into a device image, otherwise
+ * it is cleared first.  Synchronises the stream before returning.  A bad value
+ * in an epoch the call reads returns DART_E_RANGE naming it (the images are
+ * then undefined).  Calls on one streamer are serialised. */
+dart_status dart_streamer_render(dart_streamer *s, dart_dtype src_dtype, const void *emissivity,
+                                 const void *velocity, uint32_t src_flags,
+                                 const dart_view *views, int32_t n, void *const *images,
+                                 double *flux_out, uint64_t *steps_out, void *hip_stream);
+dart_status dart_streamer_get_stats(const dart_streamer *s, dart_stream_stats *out);
+dart_status dart_streamer_destroy(dart_streamer *s);
+
 /* Launch-shape parameters of the batched kernel (see dart_autotune). */
 typedef struct {
     int32_t tile_w, tile_h;  /* pixels per wavefront tile, tile_w * tile_h == 64 */

@@ -24,7 +24,9 @@ struct StackDev {
     const void *data;       // resident records
     const double *times;    // [M] epoch times (device)
     const double *inv_dt;   // [M] 1 / (t_{m+1} - t_m), 0 for the last epoch (device)
-    uint64_t epoch_stride;  // records per epoch (padded to whole bricks)
+    int64_t epoch_stride;   // records from one epoch to the next (padded to whole bricks;
+                            // negative for a streamed interval whose later epoch sits
+                            // in an earlier ring slot)
     int32_t n[3];           // cells per axis
     int32_t nb[3];          // bricks per axis
     int32_t lb[3];          // log2 of the brick shape
@@ -49,6 +51,7 @@ struct RayView {
     double ps;              // pixel scale
     double t_obs;
     double s_lo, s_hi;      // temporal window expressed in s: [t_obs - t_{M-1}, t_obs - t_0]
+    int32_t s_lo_open;      // 1: s_lo itself is outside (a streamed interval [t_m, t_{m+1}))
     double p;               // 2 + alpha
     uint32_t flags;
     int32_t width, height;

@@ -31,7 +31,8 @@ DART_ACCUMULATE = 0x80
 
 EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "dart_free_epochs",
            "dart_stack_get_info", "dart_stack_rebrick", "dart_stack_set_placement",
-           "dart_labelled_create", "dart_render", "dart_render_batch",
+           "dart_labelled_create", "dart_streamer_create", "dart_streamer_render",
+           "dart_streamer_get_stats", "dart_streamer_destroy", "dart_render", "dart_render_batch",
            "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples", "dart_count_lines",
            "dart_record_bytes", "dart_bandwidth_probe", "dart_server_create", "dart_submit",
            "dart_poll", "dart_wait", "dart_server_destroy", "dart_server_get_stats",
@@ -110,6 +111,10 @@ def _load():
         "dart_stack_rebrick": [_P, _P, _P],
         "dart_stack_set_placement": [_P, _P, _P],
         "dart_labelled_create": [_P, I32, _P],
+        "dart_streamer_create": [_P, _P, I32, _P, ctypes.c_int, I32, _P, _P],
+        "dart_streamer_render": [_P, ctypes.c_int, _P, _P, U32, _P, I32, _P, _P, _P, _P],
+        "dart_streamer_get_stats": [_P, _P],
+        "dart_streamer_destroy": [_P],
         "dart_render": [_P, _P, _P, _P, _P, _P],
         "dart_render_batch": [_P, _P, I32, _P, _P, _P, _P],
         "dart_autotune": [_P, _P, I32, I32, _P, _P, _P],
@@ -358,6 +363,73 @@ def dart_bandwidth_probe(dst, src, nbytes, reps=1, stream=None):
 class Server:
     def __init__(self, handle):
         self.handle = handle
+
+
+class dart_stream_stats(ctypes.Structure):
+    _fields_ = [("epochs_loaded", ctypes.c_int32), ("epochs_skipped", ctypes.c_int32),
+                ("intervals", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("bytes_uploaded", ctypes.c_uint64)]
+
+
+class Streamer:
+    """Owning handle of an out-of-core streamer (destroyed on GC)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            try:
+                _lib.dart_streamer_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def dart_streamer_create(dims, cell, epoch_times, storage, ring_epochs=3, brick=None) -> Streamer:
+    d = (ctypes.c_int32 * 3)(*[int(v) for v in dims])
+    c = (ctypes.c_double * 3)(*[float(v) for v in cell])
+    t = np.ascontiguousarray(epoch_times, dtype=np.float64)
+    b = (ctypes.c_int32 * 3)(*[int(v) for v in brick]) if brick is not None else None
+    out = ctypes.c_void_p()
+    _check(_load().dart_streamer_create(d, c, len(t), t.ctypes.data, storage, int(ring_epochs), b,
+                                        ctypes.byref(out)))
+    return Streamer(out.value)
+
+
+def dart_streamer_render(streamer: Streamer, emissivity, velocity, views, images, stream=None,
+                         stats=True):
+    """Out-of-core render of `views` from the epoch series in `emissivity` /
+    `velocity` (host numpy / CPU tensors, or device tensors)."""
+    jp, jdev = _ptr(emissivity)
+    bp, bdev = _ptr(velocity)
+    if jdev != bdev:
+        raise ValueError("emissivity and velocity must both be host or both be device arrays")
+    n = len(views)
+    vs = (dart_view * n)()
+    ims = (ctypes.c_void_p * n)()
+    for i, (v, im) in enumerate(zip(views, images)):
+        cv, ip = _view_for(v, im)
+        vs[i] = cv
+        ims[i] = ip
+    flux = np.zeros(n, dtype=np.float64)
+    steps = np.zeros(n, dtype=np.uint64)
+    _check(_load().dart_streamer_render(streamer.handle, _dtype_code(emissivity), jp, bp,
+                                        DART_DEVICE_PTRS if jdev else 0, vs, n, ims,
+                                        flux.ctypes.data if stats else None,
+                                        steps.ctypes.data if stats else None, _stream(stream)))
+    return (flux, steps) if stats else (None, None)
+
+
+def dart_streamer_get_stats(streamer: Streamer) -> dart_stream_stats:
+    st = dart_stream_stats()
+    _check(_load().dart_streamer_get_stats(streamer.handle, ctypes.byref(st)))
+    return st
+
+
+def dart_streamer_destroy(streamer: Streamer):
+    _check(_load().dart_streamer_destroy(streamer.handle))
+    streamer.handle = None
 
 
 def dart_server_create(hbm_budget_bytes, max_inflight=256, n_streams=3) -> Server:

@@ -60,6 +60,7 @@ def test_structs_match_header_layout():
     # dart_view: 2 doubles, 2 int32, 3 doubles, uint32 flags, 4-byte enum -> 56 bytes
     assert ctypes.sizeof(d.dart_view) == 56
     assert ctypes.sizeof(d.dart_tuning) == 24
+    assert ctypes.sizeof(d.dart.dart_stream_stats) == 24
 
 
 def test_product_does_not_reach_the_oracle():
