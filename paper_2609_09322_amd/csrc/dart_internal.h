@@ -86,9 +86,10 @@ struct BatchLaunch {
 // Host-side launchers (dart_kernels.hip).
 hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *step_acc,
                         hipStream_t s);
-// mode 0: each ray on its own; 1: depth-synchronous wavefronts
-hipError_t launch_batch(int store, bool f64_dda, int mode, const BatchLaunch &bl, int grid_blocks,
-                        hipStream_t s);
+// mode 0: each ray on its own; 1: depth-synchronous wavefronts.  labelled: the
+// launch's views are all labelled stacks (their own kernel instances)
+hipError_t launch_batch(int store, bool f64_dda, int mode, bool labelled, const BatchLaunch &bl,
+                        int grid_blocks, hipStream_t s);
 hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *bitmap, uint64_t words, unsigned long long *out,
                            hipStream_t s);

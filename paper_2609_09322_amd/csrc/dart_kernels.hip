@@ -447,20 +447,24 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
 }
 
 // Intensity of pixel (pi, pj): one march through the stack, or, for a labelled
-// stack, one march through each of its sub-domains in order, summed (emission
-// adds along the ray; sub-domains do not overlap).  The block loop is uniform
-// over the wavefront, as the depth-synchronous mode needs.
-template <int S, typename R, int SYNC>
+// stack (LAB), one march through each of its sub-domains in order, summed
+// (emission adds along the ray; sub-domains do not overlap).  The block loop
+// is uniform over the wavefront, as the depth-synchronous mode needs.
+template <int S, typename R, int SYNC, bool LAB>
 __device__ __forceinline__ double pixel_value(const RayView &v, int pi, int pj, bool in_image,
                                               uint32_t &nsteps) {
-    const int nb = v.n_blocks > 0 ? v.n_blocks : 1;
-    double acc = 0.0;
-    for (int b = 0; b < nb; b++) {
-        const StackDev &st = v.n_blocks > 0 ? v.blocks[b].st : v.st;
-        const double *centre = v.n_blocks > 0 ? v.blocks[b].centre : v.centre;
-        acc += march<S, R, SYNC>(v, st, centre, pi, pj, in_image, nsteps);
+    // (labelled stacks get kernels of their own: the block loop would
+    // otherwise raise the register count, and lower the occupancy, of every
+    // plain render)
+    if constexpr (!LAB) {
+        return march<S, R, SYNC>(v, v.st, v.centre, pi, pj, in_image, nsteps);
+    } else {
+        double acc = 0.0;
+        for (int b = 0; b < v.n_blocks; b++)
+            acc += march<S, R, SYNC>(v, v.blocks[b].st, v.blocks[b].centre, pi, pj, in_image,
+                                     nsteps);
+        return acc;
     }
-    return acc;
 }
 
 // ------------------------------------------------------------------ reductions
@@ -491,7 +495,7 @@ __device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, do
 // ------------------------------------------------------------------ kernels
 
 // Plain kernel: one thread per pixel in row order, one launch per image.
-template <int S, typename R>
+template <int S, typename R, bool LAB>
 __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
                                                unsigned long long *step_acc) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -500,7 +504,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
     uint32_t ns = 0;
     if (idx < npix) {
         const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
-        val = pixel_value<S, R, 0>(v, pi, pj, true, ns);
+        val = pixel_value<S, R, 0, LAB>(v, pi, pj, true, ns);
         store_pixel(v, pi, pj, val);
     }
     const double fs = wave_sum(val);
@@ -516,7 +520,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
 // chunks; a wave starts on chunk (block index mod n_queues), which under
 // round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
 // the other chunks when its own runs dry.
-template <int S, typename R, int SYNC>
+template <int S, typename R, int SYNC, bool LAB>
 __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
     const int lane = threadIdx.x & 63;
     const uint32_t nq = bl.n_queues;
@@ -542,7 +546,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
                        (lane >> tw_log2);
         uint32_t ns = 0;
         const bool in_image = pi < v.width && pj < v.height;
-        const double val = pixel_value<S, R, SYNC>(v, pi, pj, in_image, ns);
+        const double val = pixel_value<S, R, SYNC, LAB>(v, pi, pj, in_image, ns);
         if (in_image) store_pixel(v, pi, pj, val);
         const double fs = wave_sum(val);
         const uint32_t cs = wave_sum_u32(ns);
@@ -682,7 +686,11 @@ template <int S, typename R>
 static hipError_t plain_impl(const RayView &v, double *flux_acc, unsigned long long *step_acc,
                              hipStream_t s) {
     const uint64_t npix = (uint64_t)v.width * v.height;
-    hipLaunchKernelGGL((k_plain<S, R>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, v,
+    if (v.n_blocks > 0)
+        hipLaunchKernelGGL((k_plain<S, R, true>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0,
+                           s, v, flux_acc, step_acc);
+    else
+        hipLaunchKernelGGL((k_plain<S, R, false>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, v,
                        flux_acc, step_acc);
     return hipGetLastError();
 }
@@ -703,23 +711,30 @@ hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *
 }
 
 template <int S, typename R>
-static hipError_t batch_impl(const BatchLaunch &bl, int mode, int grid_blocks, hipStream_t s) {
+static hipError_t batch_impl(const BatchLaunch &bl, int mode, bool lab, int grid_blocks,
+                             hipStream_t s) {
     const dim3 g((unsigned)grid_blocks), b(256);
-    if (mode == 1) hipLaunchKernelGGL((k_batch<S, R, 1>), g, b, 0, s, bl);
-    else hipLaunchKernelGGL((k_batch<S, R, 0>), g, b, 0, s, bl);
+    if (lab) {
+        if (mode == 1) hipLaunchKernelGGL((k_batch<S, R, 1, true>), g, b, 0, s, bl);
+        else hipLaunchKernelGGL((k_batch<S, R, 0, true>), g, b, 0, s, bl);
+    } else {
+        if (mode == 1) hipLaunchKernelGGL((k_batch<S, R, 1, false>), g, b, 0, s, bl);
+        else hipLaunchKernelGGL((k_batch<S, R, 0, false>), g, b, 0, s, bl);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int store, bool f64, int mode, const BatchLaunch &bl, int grid_blocks,
-                        hipStream_t s) {
+hipError_t launch_batch(int store, bool f64, int mode, bool labelled, const BatchLaunch &bl,
+                        int grid_blocks, hipStream_t s) {
+    const bool L = labelled;
     switch (store) {
-        case ST_F64: return batch_impl<ST_F64, double>(bl, mode, grid_blocks, s);
-        case ST_F32: return f64 ? batch_impl<ST_F32, double>(bl, mode, grid_blocks, s)
-                                : batch_impl<ST_F32, float>(bl, mode, grid_blocks, s);
-        case ST_F16: return f64 ? batch_impl<ST_F16, double>(bl, mode, grid_blocks, s)
-                                : batch_impl<ST_F16, float>(bl, mode, grid_blocks, s);
-        case ST_BF16: return f64 ? batch_impl<ST_BF16, double>(bl, mode, grid_blocks, s)
-                                 : batch_impl<ST_BF16, float>(bl, mode, grid_blocks, s);
+        case ST_F64: return batch_impl<ST_F64, double>(bl, mode, L, grid_blocks, s);
+        case ST_F32: return f64 ? batch_impl<ST_F32, double>(bl, mode, L, grid_blocks, s)
+                                : batch_impl<ST_F32, float>(bl, mode, L, grid_blocks, s);
+        case ST_F16: return f64 ? batch_impl<ST_F16, double>(bl, mode, L, grid_blocks, s)
+                                : batch_impl<ST_F16, float>(bl, mode, L, grid_blocks, s);
+        case ST_BF16: return f64 ? batch_impl<ST_BF16, double>(bl, mode, L, grid_blocks, s)
+                                 : batch_impl<ST_BF16, float>(bl, mode, L, grid_blocks, s);
     }
     return hipErrorInvalidValue;
 }

@@ -50,6 +50,7 @@ dart_tuning tuning_for(const dart_stack *s);
 struct Group {
     int store = 0;
     bool f64 = false;
+    bool labelled = false;  // views of labelled stacks (kernels with the block loop)
     std::vector<RayView> views;
     std::vector<Tile> tiles;
     size_t view_off = 0, tile_off = 0;  // offsets in the uploaded descriptor arrays

@@ -777,13 +777,14 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         if (!images[i]) return fail(DART_E_INVAL, "images[%d] is NULL", i);
         rv.image = images[i];
         rv.acc_index = i;
-        const int key = rv.st.store * 2 + ((rv.flags & F_F64_DDA) ? 1 : 0);
+        const int key = rv.st.store * 4 + ((rv.flags & F_F64_DDA) ? 2 : 0) + (rv.n_blocks > 0 ? 1 : 0);
         auto it = gindex.find(key);
         if (it == gindex.end()) {
             it = gindex.emplace(key, groups.size()).first;
             groups.emplace_back();
             groups.back().store = rv.st.store;
             groups.back().f64 = (rv.flags & F_F64_DDA) != 0;
+            groups.back().labelled = rv.n_blocks > 0;
         }
         Group &g = groups[it->second];
         const uint32_t vi = (uint32_t)g.views.size();
@@ -875,7 +876,7 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
         bl.flux_acc = (double *)acc;
         bl.step_acc = acc + n;
         const int mode = tun.depth_sync > 0 ? 1 : 0;
-        e = launch_batch(g.store, g.f64, mode, bl, blocks, stream);
+        e = launch_batch(g.store, g.f64, mode, g.labelled, bl, blocks, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1103,8 +1104,11 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         }
         dart_status r = dart_render_batch(stacks, vv.data(), n, imgs.data(), nullptr, nullptr, hip_stream);
         if (r != DART_OK) return r;
+        // best of several replays: about 40 ms of timing per candidate, at
+        // least 2 and at most 12 replays (short batches are noisier)
         float ms_min = INFINITY;
-        for (int rep = 0; rep < 2; rep++) {
+        int reps = 2;
+        for (int rep = 0; rep < reps; rep++) {
             (void)hipEventRecord(e0, stream);
             r = dart_render_batch(stacks, vv.data(), n, imgs.data(), nullptr, nullptr, hip_stream);
             (void)hipEventRecord(e1, stream);
@@ -1113,6 +1117,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e0, e1);
             ms_min = std::min(ms_min, ms);
+            if (rep == 0) reps = std::max(2, std::min(12, (int)(40.0f / std::max(ms, 1e-3f))));
         }
         *ms_out = ms_min;
         return DART_OK;
@@ -1127,13 +1132,13 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         }
         return DART_OK;
     };
-    // Candidates within 1% of the fastest count as ties (timing noise); a tie
+    // Candidates within 2% of the fastest count as ties (timing noise); a tie
     // goes to the earliest candidate in the sweep order, so repeated tunings of
     // one workload settle on the same choice.
     auto pick = [](const std::vector<float> &ms) {
         const float lo = *std::min_element(ms.begin(), ms.end());
         for (size_t k = 0; k < ms.size(); k++)
-            if (ms[k] <= 1.01f * lo) return k;
+            if (ms[k] <= 1.02f * lo) return k;
         return (size_t)0;
     };
     double best_ms = INFINITY;

@@ -398,7 +398,7 @@ extern "C" dart_status dart_streamer_render(dart_streamer *s, dart_dtype src_dty
             bl.flux_acc = (double *)s->acc;
             bl.step_acc = s->acc + n;
             const int mode = tun.depth_sync > 0 ? 1 : 0;
-            ST_TRY(launch_batch(g.store, g.f64, mode, bl, blocks, stream), "interval kernel");
+            ST_TRY(launch_batch(g.store, g.f64, mode, g.labelled, bl, blocks, stream), "interval kernel");
         }
         for (int32_t e : {m, hi})
             if (last_use[e] == (int32_t)k) ST_TRY(hipEventRecord(s->freed[slot[e]], stream), "event");
