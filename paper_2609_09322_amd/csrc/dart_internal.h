@@ -51,7 +51,7 @@ struct RayView {
     double ps;              // pixel scale
     double t_obs;
     double s_lo, s_hi;      // temporal window expressed in s: [t_obs - t_{M-1}, t_obs - t_0]
-    int32_t s_lo_open;      // 1: s_lo itself is outside (a streamed interval [t_m, t_{m+1}))
+                            // (a half-open end is the next representable value inside)
     double p;               // 2 + alpha
     uint32_t flags;
     int32_t width, height;

@@ -266,7 +266,7 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
         const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
         if (entry >= r.stop) break;
         const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
-        if (ds > (R)0 && (v.s_lo_open ? mid > r_lo : mid >= r_lo) && mid <= r_hi) {
+        if (ds > (R)0 && mid >= r_lo && mid <= r_hi) {
             R wt = (R)v.fixed_w;
             if (lookback) {
                 bracket_seek(v, st, mid, br);
@@ -345,7 +345,6 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
     const bool single = (v.flags & F_NEAREST) || M == 1;
     const bool kahan = !(v.flags & F_NO_KAHAN);
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
-    const bool lo_open = v.s_lo_open != 0;
     const R gap = (R)v.sync_gap;
     GRaw *gdata = (GRaw *)st.data;
     const int64_t estride = st.epoch_stride;
@@ -385,8 +384,7 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                     // (the rearmost ray has entry == front, so each batch
                     // takes at least one cell or ends a ray)
                     const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
-                    const bool contrib =
-                        ds > (R)0 && (lo_open ? mid > r_lo : mid >= r_lo) && mid <= r_hi;
+                    const bool contrib = ds > (R)0 && mid >= r_lo && mid <= r_hi;
                     R wt = (R)v.fixed_w;
                     if (lookback) {
                         bracket_seek(v, st, mid, br);

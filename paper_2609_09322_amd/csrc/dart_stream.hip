@@ -300,8 +300,11 @@ extern "C" dart_status dart_streamer_render(dart_streamer *s, dart_dtype src_dty
         const bool lo_open = M > 1 && m + 1 < M - 1;
         for (Group &gr : g)
             for (RayView &rv : gr.views) {
-                const bool lookback = !(rv.flags & F_NO_LOOKBACK);
-                rv.s_lo_open = lookback && lo_open ? 1 : 0;
+                // [t_m, t_{m+1}) in t is (t_obs - t_{m+1}, t_obs - t_m] in s.  The
+                // open end becomes the next double above s_lo: the kernel's
+                // s >= s_lo test in FP64 ray parameters is then s > the end,
+                // with no extra per-cell test
+                if (!(rv.flags & F_NO_LOOKBACK) && lo_open) rv.s_lo = std::nextafter(rv.s_lo, INFINITY);
                 rv.acc_index = gidx[rv.acc_index];
             }
         gbegin.push_back(groups.size());
