@@ -369,12 +369,12 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
             break;
         }
         GRaw *addr[K];
-        R cds[K], cw[K];
+        A cds[K], cw[K];  // chord and weight, already in the accumulation type
 #pragma unroll
         for (int k = 0; k < K; k++) {
             addr[k] = gdata;  // a valid address for cells not taken in this batch
-            cds[k] = (R)0;
-            cw[k] = (R)0;
+            cds[k] = (A)0;
+            cw[k] = (A)0;
             if (alive) {
                 const R entry = fmax(r.sb0, fmax(r.sb1, r.sb2));
                 const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
@@ -404,8 +404,8 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                         wt = (R)0;
                     }
                     addr[k] = e0 + cell_offset(st, r.x, r.y, r.z);
-                    cds[k] = contrib ? ds : (R)0;
-                    cw[k] = wt;
+                    cds[k] = contrib ? (A)ds : (A)0;
+                    cw[k] = (A)wt;
                     count += contrib ? 1u : 0u;
                     budget--;
                     alive = ray_advance(st, r);
@@ -426,8 +426,8 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
         for (int k = 0; k < K; k++) {
             A val = (A)boosted<S>(r0[k], v, beaming);
             const A b1 = (A)boosted<S>(r1[k], v, beaming);
-            val = val + (A)cw[k] * (b1 - val);
-            const A term = (A)cds[k] * val;
+            val = val + cw[k] * (b1 - val);
+            const A term = cds[k] * val;
             // a zero term leaves the compensated sum as it is, so cells not
             // taken in a batch do not perturb it (rounding of sum - comp)
             if (kahan && term != (A)0) {
