@@ -75,6 +75,14 @@ typedef enum { DART_F64 = 0, DART_F32 = 1, DART_F16 = 2, DART_BF16 = 3 } dart_dt
 #define DART_DEVICE_PTRS 0x20u  /* load: field pointers are device pointers;
                                    view: the image pointer is a device pointer */
 #define DART_KERNEL_PLAIN 0x40u /* dart_render_batch: force the one-launch-per-image kernel */
+#define DART_EXACT_TIME 0x100u  /* view: cut every chord where the retarded time passes an
+                                   epoch time (and at the window ends) and weight each piece
+                                   at its own midpoint: the exact integral of the field that is
+                                   constant in each cell and linear in time between epochs,
+                                   instead of Eq. 19's one sample per cell (Eqs. 6-7, Sec. 6.1).
+                                   A cell still counts as one cell-step.  Lookback with linear
+                                   interpolation only (not with DART_NEAREST_EPOCH); not
+                                   accepted by dart_streamer_render */
 #define DART_ACCUMULATE 0x80u   /* view: add the render to the values already in the image
                                    instead of overwriting them, so partial renders of
                                    sub-domains sum into one buffer (Sec. 4, Fig. 5; Sec. 6.2).

@@ -41,6 +41,7 @@ _LIB_PATH = os.environ.get("DART_ORACLE_LIB") or os.path.join(_HERE, "liborc.so"
 NO_LOOKBACK = 1
 NO_BEAMING = 2
 NEAREST = 4
+EXACT_TIME = 8
 
 
 def build(force: bool = True) -> str:

@@ -41,7 +41,12 @@
  *
  * Flags: ORC_NO_LOOKBACK (tbar = t_obs for every cell, Eq. 3 / Eq. 10),
  * ORC_NO_BEAMING (D = 1), ORC_NEAREST (weight 1 on the epoch closest to tbar,
- * ties to the earlier epoch).
+ * ties to the earlier epoch), ORC_EXACT_TIME (every chord is also cut where
+ * the ray's retarded time passes an epoch time, s = t_obs - t_m; each piece
+ * then lies in one cell and one epoch interval, where the interpolated
+ * emissivity is linear along the ray, so the midpoint rule per piece is the
+ * exact integral of the piecewise-linear-in-time field, window ends included.
+ * A cell counts as one cell-step however many pieces it has.)
  */
 #include <math.h>
 #include <pthread.h>
@@ -52,6 +57,7 @@
 #define ORC_NO_LOOKBACK 1u
 #define ORC_NO_BEAMING 2u
 #define ORC_NEAREST 4u
+#define ORC_EXACT_TIME 8u
 
 #define ORC_DT_F64 0
 #define ORC_DT_F32 1
@@ -341,9 +347,15 @@ static double ray_sorted(const orc_grid *g, const orc_view *v, const orc_camera 
     scratch[cnt++] = s_in;
     scratch[cnt++] = s_out;
     cnt = add_crossings(g, o, d, s_in, s_out, scratch, cnt);
+    if ((v->flags & ORC_EXACT_TIME) && !(v->flags & ORC_NO_LOOKBACK))
+        for (int m = 0; m < g->n_epochs; m++) {
+            double s = v->t_obs - g->times[m];
+            if (s > s_in && s < s_out) scratch[cnt++] = s;
+        }
     qsort(scratch, (size_t)cnt, sizeof(double), cmp_double);
     double acc = 0.0;
     long long n_steps = 0;
+    long long last_cell = -1;  /* a cell cut in pieces counts once */
     for (int q = 0; q + 1 < cnt; q++) {
         double sa = scratch[q], sb = scratch[q + 1];
         if (!(sb > sa)) continue;
@@ -355,8 +367,12 @@ static double ray_sorted(const orc_grid *g, const orc_view *v, const orc_camera 
         }
         if (!inside) continue;
         int r = cell_term(g, v, d, idx[0], idx[1], idx[2], sa, sb, &acc);
+        const long long lin = ((long long)idx[2] * g->n[1] + idx[1]) * g->n[0] + idx[0];
         if (r < 0) tl_err = 1;
-        else n_steps += r;
+        else if (r > 0 && lin != last_cell) {
+            n_steps++;
+            last_cell = lin;
+        }
     }
     if (steps) *steps += n_steps;
     return acc;
@@ -377,9 +393,24 @@ static double ray_brute(const orc_grid *g, const orc_view *v, const orc_camera *
                 double hi[3] = {(ix + 1) * g->cell[0], (iy + 1) * g->cell[1], (iz + 1) * g->cell[2]};
                 double sa, sb;
                 if (!ray_box(o, d, lo, hi, &sa, &sb)) continue;
-                int r = cell_term(g, v, d, ix, iy, iz, sa, sb, &acc);
-                if (r < 0) tl_err = 1;
-                else n_steps += r;
+                /* exact-time mode: the chord cut at every epoch time inside it */
+                double cuts[2 + 64];  /* (exact-time brute force: at most 64 epochs) */
+                int nc = 0;
+                cuts[nc++] = sa;
+                if ((v->flags & ORC_EXACT_TIME) && !(v->flags & ORC_NO_LOOKBACK))
+                    for (int m = 0; m < g->n_epochs && m < 64; m++) {
+                        double s = v->t_obs - g->times[m];
+                        if (s > sa && s < sb) cuts[nc++] = s;
+                    }
+                cuts[nc++] = sb;
+                qsort(cuts, (size_t)nc, sizeof(double), cmp_double);
+                int any = 0;
+                for (int q = 0; q + 1 < nc; q++) {
+                    int r = cell_term(g, v, d, ix, iy, iz, cuts[q], cuts[q + 1], &acc);
+                    if (r < 0) tl_err = 1;
+                    else any |= r;
+                }
+                n_steps += any;
             }
     if (steps) *steps += n_steps;
     return acc;
@@ -405,7 +436,7 @@ static void *worker(void *arg) {
     const orc_grid *g = jb->g;
     tl_win = jb->win;
     tl_err = 0;
-    size_t cap = 2 + (size_t)g->n[0] + g->n[1] + g->n[2];
+    size_t cap = 2 + (size_t)g->n[0] + g->n[1] + g->n[2] + (size_t)g->n_epochs;
     double *scratch = (double *)malloc(cap * sizeof(double));
     for (long long q = jb->tid; q < jb->n_pix; q += jb->nthreads) {
         int i, j;

@@ -15,6 +15,7 @@ enum : uint32_t {
     F_F64_DDA = 0x10u,
     F_DEVICE_PTRS = 0x20u,
     F_ACCUMULATE = 0x80u,
+    F_EXACT = 0x100u,
 };
 
 // Resident stack as the kernels see it.  Records (j, bx, by, bz) are stored
@@ -86,9 +87,10 @@ struct BatchLaunch {
 // Host-side launchers (dart_kernels.hip).
 hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *step_acc,
                         hipStream_t s);
-// mode 0: each ray on its own; 1: depth-synchronous wavefronts.  labelled: the
-// launch's views are all labelled stacks (their own kernel instances)
-hipError_t launch_batch(int store, bool f64_dda, int mode, bool labelled, const BatchLaunch &bl,
+// Kernel variant bits: 1 depth-synchronous wavefronts, 2 the launch's views are
+// labelled stacks (block loop), 4 exact temporal integration.
+enum : int { KV_SYNC = 1, KV_LABELLED = 2, KV_EXACT = 4 };
+hipError_t launch_batch(int store, bool f64_dda, int variant, const BatchLaunch &bl,
                         int grid_blocks, hipStream_t s);
 hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *bitmap, uint64_t words, unsigned long long *out,

@@ -244,6 +244,20 @@ __device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &s
     }
 }
 
+// Exact-time pieces start at s: the bracket of the retarded times just below
+// t_obs - s, so a piece that starts on an epoch time takes the earlier interval.
+template <typename R>
+__device__ __forceinline__ void bracket_seek_from(const RayView &v, const StackDev &st, R s,
+                                                  Bracket<R> &b) {
+    gdouble *t = (gdouble *)st.times, *idt = (gdouble *)st.inv_dt;
+    while (b.m > 0 && s >= b.am) {
+        b.m--;
+        b.am1 = b.am;
+        b.am = (R)(v.t_obs - t[b.m]);
+        b.inv_dt = (R)idt[b.m];
+    }
+}
+
 // Sample marking for the compulsory-bytes count: sets the (epoch, cell) bits
 // of positive weight in `bitmap` ([M][nz][ny][nx] bits).
 // line_log2 >= 0 marks instead the 128-byte lines of the resident layout that
@@ -328,7 +342,13 @@ __device__ __forceinline__ R wave_min(R x) {
 //      instead of some batches apart.  Every lane then stays in the loop
 //      until all rays of the wavefront have ended, including lanes whose ray
 //      misses the grid.
-template <int S, typename R, int SYNC>
+// EX (exact temporal integration): a cell's chord is cut where the ray's
+// retarded time passes an epoch time and at the window ends; each piece lies
+// in one epoch interval, where the interpolated field is linear along the ray,
+// so the midpoint value times the piece is its exact integral.  A batch slot
+// then takes one piece instead of one cell; a cell counts as one cell-step.
+// (Linear interpolation with lookback only: the host clears EX otherwise.)
+template <int S, typename R, int SYNC, bool EX>
 __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                                         const double *centre, int pi, int pj, bool in_image,
                                         uint32_t &nsteps) {
@@ -359,6 +379,8 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
     uint32_t count = 0;
     // a ray crosses at most n0 + n1 + n2 - 2 cells
     int budget = st.n[0] + st.n[1] + st.n[2] + 3;
+    R piece = -(R)INFINITY;  // EX: start of the part of the current cell not yet taken
+    bool cell_counted = false;
 
     for (;;) {
         R front = (R)0;
@@ -380,7 +402,41 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                 const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
                 if (entry >= r.stop || budget <= 0) {
                     alive = false;
-                } else if (SYNC == 0 || entry - front < gap || entry <= front) {
+                } else if (EX && (SYNC == 0 || entry - front < gap || entry <= front)) {
+                    // one piece [a, b] of the cell: from where the last piece
+                    // ended (or the cell's entry, or the window's start) to the
+                    // next epoch time or the end of cell or window
+                    const R a = fmax(fmax(entry, piece), r_lo);
+                    const R end = fmin(exit, r_hi);
+                    bool more = false;
+                    R b = a;
+                    if (a < end) {
+                        // bracket of the retarded times just below t_obs - a
+                        bracket_seek_from(v, st, a, br);
+                        b = fmin(end, br.am);
+                        more = b < end;
+                    }
+                    const R ds = b - a, mid = (R)0.5 * (a + b);
+                    const bool contrib = ds > (R)0;
+                    const R wt = (br.am - mid) * br.inv_dt;
+                    if (br.m != ebase_m) {
+                        ebase = gdata + (int64_t)br.m * estride;
+                        ebase_m = br.m;
+                    }
+                    addr[k] = ebase + cell_offset(st, r.x, r.y, r.z);
+                    cds[k] = contrib ? (A)ds : (A)0;
+                    cw[k] = (A)wt;
+                    count += (contrib && !cell_counted) ? 1u : 0u;
+                    cell_counted |= contrib;
+                    if (more) {
+                        piece = b;
+                    } else {
+                        piece = -(R)INFINITY;
+                        cell_counted = false;
+                        budget--;
+                        alive = ray_advance(st, r);
+                    }
+                } else if (!EX && (SYNC == 0 || entry - front < gap || entry <= front)) {
                     // (the rearmost ray has entry == front, so each batch
                     // takes at least one cell or ends a ray)
                     const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
@@ -448,19 +504,19 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
 // stack (LAB), one march through each of its sub-domains in order, summed
 // (emission adds along the ray; sub-domains do not overlap).  The block loop
 // is uniform over the wavefront, as the depth-synchronous mode needs.
-template <int S, typename R, int SYNC, bool LAB>
+template <int S, typename R, int SYNC, bool LAB, bool EX>
 __device__ __forceinline__ double pixel_value(const RayView &v, int pi, int pj, bool in_image,
                                               uint32_t &nsteps) {
     // (labelled stacks get kernels of their own: the block loop would
     // otherwise raise the register count, and lower the occupancy, of every
     // plain render)
     if constexpr (!LAB) {
-        return march<S, R, SYNC>(v, v.st, v.centre, pi, pj, in_image, nsteps);
+        return march<S, R, SYNC, EX>(v, v.st, v.centre, pi, pj, in_image, nsteps);
     } else {
         double acc = 0.0;
         for (int b = 0; b < v.n_blocks; b++)
-            acc += march<S, R, SYNC>(v, v.blocks[b].st, v.blocks[b].centre, pi, pj, in_image,
-                                     nsteps);
+            acc += march<S, R, SYNC, EX>(v, v.blocks[b].st, v.blocks[b].centre, pi, pj,
+                                         in_image, nsteps);
         return acc;
     }
 }
@@ -493,7 +549,7 @@ __device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, do
 // ------------------------------------------------------------------ kernels
 
 // Plain kernel: one thread per pixel in row order, one launch per image.
-template <int S, typename R, bool LAB>
+template <int S, typename R, bool LAB, bool EX>
 __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
                                                unsigned long long *step_acc) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -502,7 +558,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
     uint32_t ns = 0;
     if (idx < npix) {
         const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
-        val = pixel_value<S, R, 0, LAB>(v, pi, pj, true, ns);
+        val = pixel_value<S, R, 0, LAB, EX>(v, pi, pj, true, ns);
         store_pixel(v, pi, pj, val);
     }
     const double fs = wave_sum(val);
@@ -518,7 +574,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
 // chunks; a wave starts on chunk (block index mod n_queues), which under
 // round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
 // the other chunks when its own runs dry.
-template <int S, typename R, int SYNC, bool LAB>
+template <int S, typename R, int SYNC, bool LAB, bool EX>
 __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
     const int lane = threadIdx.x & 63;
     const uint32_t nq = bl.n_queues;
@@ -544,7 +600,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
                        (lane >> tw_log2);
         uint32_t ns = 0;
         const bool in_image = pi < v.width && pj < v.height;
-        const double val = pixel_value<S, R, SYNC, LAB>(v, pi, pj, in_image, ns);
+        const double val = pixel_value<S, R, SYNC, LAB, EX>(v, pi, pj, in_image, ns);
         if (in_image) store_pixel(v, pi, pj, val);
         const double fs = wave_sum(val);
         const uint32_t cs = wave_sum_u32(ns);
@@ -683,13 +739,12 @@ static inline unsigned grid_for(uint64_t n, unsigned cap = 1u << 16) {
 template <int S, typename R>
 static hipError_t plain_impl(const RayView &v, double *flux_acc, unsigned long long *step_acc,
                              hipStream_t s) {
-    const uint64_t npix = (uint64_t)v.width * v.height;
-    if (v.n_blocks > 0)
-        hipLaunchKernelGGL((k_plain<S, R, true>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0,
-                           s, v, flux_acc, step_acc);
-    else
-        hipLaunchKernelGGL((k_plain<S, R, false>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, v,
-                       flux_acc, step_acc);
+    const dim3 g((unsigned)(((uint64_t)v.width * v.height + 255) / 256)), b(256);
+    const bool lab = v.n_blocks > 0, ex = (v.flags & F_EXACT) != 0;
+    if (lab && ex) hipLaunchKernelGGL((k_plain<S, R, true, true>), g, b, 0, s, v, flux_acc, step_acc);
+    else if (lab) hipLaunchKernelGGL((k_plain<S, R, true, false>), g, b, 0, s, v, flux_acc, step_acc);
+    else if (ex) hipLaunchKernelGGL((k_plain<S, R, false, true>), g, b, 0, s, v, flux_acc, step_acc);
+    else hipLaunchKernelGGL((k_plain<S, R, false, false>), g, b, 0, s, v, flux_acc, step_acc);
     return hipGetLastError();
 }
 
@@ -709,30 +764,31 @@ hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *
 }
 
 template <int S, typename R>
-static hipError_t batch_impl(const BatchLaunch &bl, int mode, bool lab, int grid_blocks,
-                             hipStream_t s) {
+static hipError_t batch_impl(const BatchLaunch &bl, int variant, int grid_blocks, hipStream_t s) {
     const dim3 g((unsigned)grid_blocks), b(256);
-    if (lab) {
-        if (mode == 1) hipLaunchKernelGGL((k_batch<S, R, 1, true>), g, b, 0, s, bl);
-        else hipLaunchKernelGGL((k_batch<S, R, 0, true>), g, b, 0, s, bl);
-    } else {
-        if (mode == 1) hipLaunchKernelGGL((k_batch<S, R, 1, false>), g, b, 0, s, bl);
-        else hipLaunchKernelGGL((k_batch<S, R, 0, false>), g, b, 0, s, bl);
+    switch (variant & 7) {
+        case 0: hipLaunchKernelGGL((k_batch<S, R, 0, false, false>), g, b, 0, s, bl); break;
+        case 1: hipLaunchKernelGGL((k_batch<S, R, 1, false, false>), g, b, 0, s, bl); break;
+        case 2: hipLaunchKernelGGL((k_batch<S, R, 0, true, false>), g, b, 0, s, bl); break;
+        case 3: hipLaunchKernelGGL((k_batch<S, R, 1, true, false>), g, b, 0, s, bl); break;
+        case 4: hipLaunchKernelGGL((k_batch<S, R, 0, false, true>), g, b, 0, s, bl); break;
+        case 5: hipLaunchKernelGGL((k_batch<S, R, 1, false, true>), g, b, 0, s, bl); break;
+        case 6: hipLaunchKernelGGL((k_batch<S, R, 0, true, true>), g, b, 0, s, bl); break;
+        default: hipLaunchKernelGGL((k_batch<S, R, 1, true, true>), g, b, 0, s, bl); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int store, bool f64, int mode, bool labelled, const BatchLaunch &bl,
-                        int grid_blocks, hipStream_t s) {
-    const bool L = labelled;
+hipError_t launch_batch(int store, bool f64, int variant, const BatchLaunch &bl, int grid_blocks,
+                        hipStream_t s) {
     switch (store) {
-        case ST_F64: return batch_impl<ST_F64, double>(bl, mode, L, grid_blocks, s);
-        case ST_F32: return f64 ? batch_impl<ST_F32, double>(bl, mode, L, grid_blocks, s)
-                                : batch_impl<ST_F32, float>(bl, mode, L, grid_blocks, s);
-        case ST_F16: return f64 ? batch_impl<ST_F16, double>(bl, mode, L, grid_blocks, s)
-                                : batch_impl<ST_F16, float>(bl, mode, L, grid_blocks, s);
-        case ST_BF16: return f64 ? batch_impl<ST_BF16, double>(bl, mode, L, grid_blocks, s)
-                                 : batch_impl<ST_BF16, float>(bl, mode, L, grid_blocks, s);
+        case ST_F64: return batch_impl<ST_F64, double>(bl, variant, grid_blocks, s);
+        case ST_F32: return f64 ? batch_impl<ST_F32, double>(bl, variant, grid_blocks, s)
+                                : batch_impl<ST_F32, float>(bl, variant, grid_blocks, s);
+        case ST_F16: return f64 ? batch_impl<ST_F16, double>(bl, variant, grid_blocks, s)
+                                : batch_impl<ST_F16, float>(bl, variant, grid_blocks, s);
+        case ST_BF16: return f64 ? batch_impl<ST_BF16, double>(bl, variant, grid_blocks, s)
+                                 : batch_impl<ST_BF16, float>(bl, variant, grid_blocks, s);
     }
     return hipErrorInvalidValue;
 }

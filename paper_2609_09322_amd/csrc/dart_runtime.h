@@ -51,6 +51,7 @@ struct Group {
     int store = 0;
     bool f64 = false;
     bool labelled = false;  // views of labelled stacks (kernels with the block loop)
+    bool exact = false;     // views with exact temporal integration
     std::vector<RayView> views;
     std::vector<Tile> tiles;
     size_t view_off = 0, tile_off = 0;  // offsets in the uploaded descriptor arrays

@@ -508,8 +508,11 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
         return fail(DART_E_INVAL, "FP64 images need an FP64 stack");
     if (v->flags & ~(uint32_t)(DART_NO_LOOKBACK | DART_NO_BEAMING | DART_NEAREST_EPOCH |
                                DART_NO_KAHAN | DART_FORCE_F64_DDA | DART_DEVICE_PTRS |
-                               DART_ACCUMULATE))
+                               DART_ACCUMULATE | DART_EXACT_TIME))
         return fail(DART_E_INVAL, "unknown view flags 0x%x", v->flags);
+    if ((v->flags & DART_EXACT_TIME) && (v->flags & DART_NEAREST_EPOCH))
+        return fail(DART_E_INVAL, "DART_EXACT_TIME integrates the linear interpolation; "
+                                  "it does not combine with DART_NEAREST_EPOCH");
     if ((v->flags & DART_ACCUMULATE) && !(v->flags & DART_DEVICE_PTRS))
         return fail(DART_E_INVAL, "DART_ACCUMULATE needs a device image (DART_DEVICE_PTRS)");
     memset(rv, 0, sizeof(*rv));
@@ -535,6 +538,10 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     rv->p = 2.0 + v->alpha;
     rv->flags = v->flags & (F_NO_LOOKBACK | F_NO_BEAMING | F_NEAREST | F_NO_KAHAN | F_F64_DDA |
                             F_ACCUMULATE);
+    // exact temporal integration only changes anything with lookback and
+    // more than one epoch
+    if ((v->flags & DART_EXACT_TIME) && !(v->flags & DART_NO_LOOKBACK) && s->dev.n_epochs > 1)
+        rv->flags |= F_EXACT;
     // FP64 ray parameters (plane crossings, chord midpoints) when a ray may
     // cross more than ~4k cells, and for FP32 stacks: FP32 crossings of
     // magnitude ~L/2 carry ~1e-5 absolute rounding, which chords at jumps of
@@ -777,7 +784,8 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         if (!images[i]) return fail(DART_E_INVAL, "images[%d] is NULL", i);
         rv.image = images[i];
         rv.acc_index = i;
-        const int key = rv.st.store * 4 + ((rv.flags & F_F64_DDA) ? 2 : 0) + (rv.n_blocks > 0 ? 1 : 0);
+        const int key = rv.st.store * 8 + ((rv.flags & F_F64_DDA) ? 4 : 0) +
+                        (rv.n_blocks > 0 ? 2 : 0) + ((rv.flags & F_EXACT) ? 1 : 0);
         auto it = gindex.find(key);
         if (it == gindex.end()) {
             it = gindex.emplace(key, groups.size()).first;
@@ -785,6 +793,7 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             groups.back().store = rv.st.store;
             groups.back().f64 = (rv.flags & F_F64_DDA) != 0;
             groups.back().labelled = rv.n_blocks > 0;
+            groups.back().exact = (rv.flags & F_EXACT) != 0;
         }
         Group &g = groups[it->second];
         const uint32_t vi = (uint32_t)g.views.size();
@@ -875,8 +884,9 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
         bl.n_queues = g.n_queues;
         bl.flux_acc = (double *)acc;
         bl.step_acc = acc + n;
-        const int mode = tun.depth_sync > 0 ? 1 : 0;
-        e = launch_batch(g.store, g.f64, mode, g.labelled, bl, blocks, stream);
+        const int variant = (tun.depth_sync > 0 ? KV_SYNC : 0) | (g.labelled ? KV_LABELLED : 0) |
+                            (g.exact ? KV_EXACT : 0);
+        e = launch_batch(g.store, g.f64, variant, bl, blocks, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -198,6 +198,10 @@ extern "C" dart_status dart_streamer_render(dart_streamer *s, dart_dtype src_dty
     if (src_dtype != DART_F64 && src_dtype != DART_F32)
         return fail(DART_E_INVAL, "src_dtype must be DART_F64 or DART_F32");
     if (src_flags & ~(uint32_t)DART_DEVICE_PTRS) return fail(DART_E_INVAL, "unknown source flags");
+    for (int32_t i = 0; i < n; i++)
+        if (views[i].flags & DART_EXACT_TIME)
+            return fail(DART_E_INVAL, "view %d: DART_EXACT_TIME is not streamed (a cell cut by an "
+                        "interval boundary would count in both intervals)", i);
     std::lock_guard<std::mutex> lock(s->mu);
     hipStream_t stream = (hipStream_t)hip_stream;
     const int32_t M = s->M, R = s->ring_n;
@@ -400,8 +404,8 @@ extern "C" dart_status dart_streamer_render(dart_streamer *s, dart_dtype src_dty
             bl.n_queues = g.n_queues;
             bl.flux_acc = (double *)s->acc;
             bl.step_acc = s->acc + n;
-            const int mode = tun.depth_sync > 0 ? 1 : 0;
-            ST_TRY(launch_batch(g.store, g.f64, mode, g.labelled, bl, blocks, stream), "interval kernel");
+            const int variant = (tun.depth_sync > 0 ? KV_SYNC : 0) | (g.labelled ? KV_LABELLED : 0);
+            ST_TRY(launch_batch(g.store, g.f64, variant, bl, blocks, stream), "interval kernel");
         }
         for (int32_t e : {m, hi})
             if (last_use[e] == (int32_t)k) ST_TRY(hipEventRecord(s->freed[slot[e]], stream), "event");

@@ -28,6 +28,7 @@ DART_FORCE_F64_DDA = 0x10
 DART_DEVICE_PTRS = 0x20
 DART_KERNEL_PLAIN = 0x40
 DART_ACCUMULATE = 0x80
+DART_EXACT_TIME = 0x100
 
 EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "dart_free_epochs",
            "dart_stack_get_info", "dart_stack_rebrick", "dart_stack_set_placement",

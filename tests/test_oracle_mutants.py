@@ -70,6 +70,10 @@ MUTANTS = {
                                   "double nhat[3] = {st * sp, st * cp, ct};")],
     "centre_off_by_half_cell": [(": 0.5 * g->n[a] * g->cell[a];",
                                  ": 0.5 * (g->n[a] + 1) * g->cell[a];")],
+    # exact temporal integration
+    "exact_cut_sign": [("double s = v->t_obs - g->times[m];\n            if (s > s_in && s < s_out)",
+                        "double s = v->t_obs + g->times[m];\n            if (s > s_in && s < s_out)")],
+    "exact_counts_pieces": [("else if (r > 0 && lin != last_cell) {", "else if (r > 0) {")],
     # sub-domains (labelled mode)
     "placement_origin_sign": [("g->placed ? g->centre[a] - g->origin[a]",
                                "g->placed ? g->centre[a] + g->origin[a]")],

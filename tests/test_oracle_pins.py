@@ -302,6 +302,58 @@ def test_p7_midpoint_error_bound(orc):
     assert bound > 2 * h * np.abs(j).max() * (len(seg) + 1)
 
 
+# ---------------------------------------------------------------- P16 exact temporal integration
+
+def test_p16_exact_time_matches_quadrature(orc):
+    """Exact-time mode: cutting every chord at the epoch times leaves pieces on
+    which the interpolated field is linear along the ray, so O1 then equals
+    the continuous integral (O3) up to the quadrature's own error at the cell
+    faces, where the midpoint-sampled O1 of P7 misses by the kink terms.
+    (Epoch times not symmetric about t_obs, so that a cut at t_obs + t_m
+    instead of t_obs - t_m would land elsewhere.)"""
+    n = 7
+    j, beta, t = synth.random_stack((n, n, n), 9, seed=4, beta_max=0.0,
+                                    times=np.linspace(-5.3, 6.7, 9))
+    s = _stack(orc, j, beta, t)
+    v = orc.View(52.0, 33.0, 9, 9, 1.25, 0.0, 0.0, orc.NO_BEAMING)
+    ve = orc.View(52.0, 33.0, 9, 9, 1.25, 0.0, 0.0, orc.NO_BEAMING | orc.EXACT_TIME)
+    mid, _ = orc.render(s, v, threads=1)
+    ex, _ = orc.render(s, ve, threads=1)
+    h = 2e-5
+    worse = 0
+    for (i, jj) in [(4, 4), (2, 5), (6, 3), (5, 6)]:
+        seg = orc.segments(s, v, i, jj)
+        jump_bound = 2 * h * np.abs(j).max() * (len(seg) + 2 + len(t))
+        q = orc.quadrature(s, v, i, jj, h=h)
+        assert abs(ex[jj, i] - q) <= jump_bound
+        worse += abs(mid[jj, i] - q) > jump_bound
+    assert worse >= 1
+
+
+@pytest.mark.parametrize("flags", [0, "beam"])
+def test_p16_exact_time_brute_force_and_linear_fields(orc, flags):
+    """O1 and O2 agree in exact-time mode (sorted cuts vs per-cell boxes cut at
+    the epoch times), and for fields linear in time the two modes agree (the
+    midpoint rule is already exact there)."""
+    fl = orc.NO_BEAMING if flags == 0 else 0
+    j, beta, t = synth.random_stack((6, 5, 7), 6, seed=12, beta_max=0.7,
+                                    times=np.linspace(-3.6, 4.4, 6))
+    s = _stack(orc, j, beta, t)
+    for th, ph in [(37.0, 211.0), (90.0, 0.0), (123.0, 300.0)]:
+        v = orc.View(th, ph, 14, 12, 0.8, 0.3, 0.7, fl | orc.EXACT_TIME)
+        a, na = orc.render(s, v)
+        b, nb = orc.render_brute(s, v)
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+        assert na == nb
+    # linear in time, static beta: both modes give the exact integral
+    (jl, bl), _, tl, _ = labelled_refinement_case()
+    sl = _stack(orc, jl, bl, tl)
+    for th, ph in [(35.0, 20.0), (128.0, 300.0)]:
+        m, _ = orc.render(sl, orc.View(th, ph, 30, 28, 0.5, 0.0, 0.7, 0))
+        e, _ = orc.render(sl, orc.View(th, ph, 30, 28, 0.5, 0.0, 0.7, orc.EXACT_TIME))
+        assert np.abs(m - e).max() <= 1e-12 * np.abs(m).max()
+
+
 # ---------------------------------------------------------------- P8 fast-light limit
 
 def test_p8_fast_light_limit(orc):
