@@ -185,7 +185,7 @@ def oracle_sample(host, times, views, n_rays, seed, threads, kind="f32"):
         pix = np.stack([rng.integers(0, v.width, per_view), rng.integers(0, v.height, per_view)],
                        axis=1).astype(np.int32)
         ov = oracle.View(v.theta_deg, v.phi_deg, v.width, v.height, v.pixel_scale, v.t_obs,
-                         v.alpha, v.flags & 7)
+                         v.alpha, (v.flags & 7) | (oracle.EXACT_TIME if v.flags & 0x100 else 0))
         t0 = time.perf_counter()
         val, n = oracle.render(ost, ov, pixels=pix, threads=threads)
         secs += time.perf_counter() - t0
@@ -204,12 +204,13 @@ def pix_err(got, ref, img_max):
 def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_spec, gamma,
                         knots, seed, rec_bytes, dtype_name, check_views=None, tune_views=None):
     stream = torch.cuda.Stream()
-    wkey = args.workload if args.workload != "batch" else f"batch-{args.storage}"
+    wkey = (args.workload if args.workload != "batch" else f"batch-{args.storage}") + ("-exact" if args.exact_time else "")
     keep_host = not args.no_cpu_baseline or args.check
     st, times, host = make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage,
                                      dtype_name, keep_host)
     L = math.sqrt(sum(float(d) ** 2 for d in dims))
-    views = [dart.View(th, ph, P, P, L / P, 0.0, alpha) for th, ph, P, alpha in views_spec]
+    vflags = dart.DART_EXACT_TIME if args.exact_time else 0
+    views = [dart.View(th, ph, P, P, L / P, 0.0, alpha, vflags) for th, ph, P, alpha in views_spec]
     imgs = [torch.zeros((v.height, v.width), dtype=torch.float32, device="cuda") for v in views]
     stacks = [st] * len(views)
     n_img = len(views)
@@ -927,6 +928,9 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gb", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--exact-time", action="store_true",
+                    help="jet / batch workloads: views with DART_EXACT_TIME (chords cut at "
+                         "epoch times)")
     ap.add_argument("--check", action="store_true", default=True)
     ap.add_argument("--no-check", dest="check", action="store_false")
     ap.add_argument("--check-rays", type=int, default=2048)
@@ -944,7 +948,7 @@ def main():
                          "of a --profile run (with the same --workload/--storage/--tuning)")
     args = ap.parse_args()
     if args.pmc_summary:
-        wkey = args.workload if args.workload != "batch" else f"batch-{args.storage}"
+        wkey = (args.workload if args.workload != "batch" else f"batch-{args.storage}") + ("-exact" if args.exact_time else "")
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], wkey, normalise_tuning(args.tuning))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
