@@ -99,6 +99,17 @@ def measured_traffic(workload, tuning):
     return None, f"no counter row for {workload}, tuning {key}, kernel {kid}"
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
@@ -260,9 +271,20 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
         log(f"plain: {pms:.3f} ms/step")
         torch.cuda.synchronize()
         same = all(torch.equal(a, b) for a, b in zip(imgs, plain_imgs))
+        # the plain kernel with a host synchronisation after every image
+        def plain_sync():
+            for v, im in zip(views, plain_imgs):
+                dart.dart_render(st, v, im, stream=stream, stats=False)
+                stream.synchronize()
+
+        swall, _ = time_steps(torch, stream, plain_sync, max(1, args.steps // 2), 1)
+        sms = 1e3 * swall / max(1, args.steps // 2)
         res["plain"] = {"ms_per_step": pms, "images_per_s": n_img / (pms * 1e-3),
                         "cell_steps_per_s": cell_steps / (pms * 1e-3),
-                        "identical_to_batched": bool(same)}
+                        "identical_to_batched": bool(same),
+                        "synchronised_ms_per_step": sms,
+                        "note": "one launch per image back to back on one stream (the stronger "
+                                "of the two); synchronised: a host wait after every image"}
         # the same batched call handing back pinned host images (the render
         # waits for its device-to-host copies): the PCIe-inclusive rate
         host_imgs = [torch.empty((v.height, v.width), dtype=torch.float32, pin_memory=True)
@@ -301,10 +323,16 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
         _, n0, s0 = oracle_sample(host, times, views, cal, 11, threads, dtype_name)
         rays = int(min(1 << 25, max(cal, cal * 15.0 / max(s0, 1e-3))))
         _, n1, s1 = oracle_sample(host, times, views, rays, 12, threads, dtype_name)
+        # and on one core, over a sample of ~5 s
+        r1 = max(n_img, int(rays * 5.0 / max(s1 * threads, 1e-3)))
+        _, m1, t1 = oracle_sample(host, times, views, r1, 13, 1, dtype_name)
         cpu = {"value": n1 / s1, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{rays} random pixels over the {n_img} views ({n1} cell-steps, {s1:.1f} s)",
-               "images_per_s_equiv": (n1 / s1) / (cell_steps / n_img)}
-        log(f"cpu oracle: {n1 / s1:.3e} cell-steps/s on {threads} threads")
+               "images_per_s_equiv": (n1 / s1) / (cell_steps / n_img),
+               "one_core": {"value": m1 / t1, "sample": f"{r1} random pixels ({m1} cell-steps, "
+                                                       f"{t1:.1f} s)"},
+               "cpu_model": cpu_model()}
+        log(f"cpu oracle: {n1 / s1:.3e} cell-steps/s on {threads} threads, {m1 / t1:.3e} on one")
 
     # in profile mode a 1 GiB copy (2 launches) runs as the counter calibration kernel
     bw = bandwidth_probe(dart, torch, stream, nbytes=(1 << 30) if args.profile else (4 << 30),

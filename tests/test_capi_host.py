@@ -52,6 +52,25 @@ def test_library_loads_and_reports_errors_without_gpu():
     assert "NULL" in d.dart_last_error() or "null" in d.dart_last_error().lower()
     rc = lib.dart_server_create(ctypes.c_size_t(10), 1, 1, None)
     assert rc == d.DART_E_INVAL
+    # the entry points added for sub-domains, labelled stacks and streaming
+    # also check their arguments before touching a device
+    origin = (ctypes.c_double * 3)(0, 0, 0)
+    assert lib.dart_stack_set_placement(None, origin, origin) == d.DART_E_INVAL
+    out = ctypes.c_void_p(1)
+    assert lib.dart_labelled_create(None, 0, ctypes.byref(out)) == d.DART_E_INVAL
+    assert out.value is None
+    dims = (ctypes.c_int32 * 3)(4, 4, 4)
+    cell = (ctypes.c_double * 3)(1, 1, 1)
+    t = (ctypes.c_double * 2)(0.0, 1.0)
+    out = ctypes.c_void_p(1)
+    assert lib.dart_streamer_create(dims, cell, 2, t, d.DART_F32, 2, None,
+                                    ctypes.byref(out)) == d.DART_E_INVAL
+    assert "ring_epochs" in d.dart_last_error()
+    assert out.value is None
+    assert lib.dart_streamer_render(None, d.DART_F32, None, None, 0, None, 0, None, None, None,
+                                    None) == d.DART_E_INVAL
+    assert lib.dart_streamer_destroy(None) == d.DART_E_INVAL
+    assert lib.dart_count_lines(None, None, None, None) == d.DART_E_INVAL
 
 
 def test_structs_match_header_layout():
