@@ -1084,7 +1084,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
     // Measured on MI355X: the L2 working set of the resident waves dominates,
     // so the sweep covers low occupancies, row-like tiles and both spatial orders.
     const int shapes[][2] = {{64, 1}, {32, 2}, {16, 4}, {8, 8}};
-    const int waves[] = {8, 12, 16};
+    const int waves[] = {12, 16, 8};  // (ties go to the earliest: 12 first)
     const int orders[] = {0, 1, 2};
     for (auto &sh : shapes)
         for (int w : waves)
