@@ -266,7 +266,9 @@ typedef struct {
     int32_t tile_w, tile_h;  /* pixels per wavefront tile, tile_w * tile_h == 64 */
     int32_t waves_per_cu;    /* resident waves per compute unit for the persistent grid */
     int32_t order;           /* tile queue order: 0 row-major, 1 longest estimated tile
-                                first, 2 Z-order (Morton) */
+                                first, 2 Z-order (Morton), 3 rows from the image's middle
+                                outward (the upper half upward, then the lower half
+                                downward) */
     int32_t orient;          /* 1: per view, turn the tile so that its long side follows
                                 the image-plane projection of the bricks' long axis
                                 (lanes of a wavefront then share cache lines) */

@@ -220,27 +220,56 @@ struct Bracket {
 };
 
 typedef const double __attribute__((address_space(1))) gdouble;
+typedef double __attribute__((address_space(3))) ldsdouble;
+
+// Epoch table of a view in LDS, one per wavefront: (t_obs - t_m, 1 / (t_{m+1} -
+// t_m)) for m < n_epochs, so that a lane whose bracket moves reads it from LDS
+// instead of waiting on a global load in the middle of a batch.  Views with
+// more epochs read global memory (the same values).
+constexpr int EPOCH_TAB_MAX = 64;
+
+// Fills the calling wavefront's table for stack st seen at t_obs (all lanes).
+__device__ __forceinline__ void epoch_tab_fill(ldsdouble *tab, const StackDev &st, double t_obs) {
+    gdouble *t = (gdouble *)st.times, *idt = (gdouble *)st.inv_dt;
+    const int lane = threadIdx.x & 63;
+    for (int m = lane; m < st.n_epochs; m += 64) {
+        tab[2 * m] = t_obs - t[m];
+        tab[2 * m + 1] = idt[m];
+    }
+    // the wavefront's own writes, before any lane reads another lane's entry
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename R>
+__device__ __forceinline__ R epoch_a(const RayView &v, const StackDev &st, const ldsdouble *tab,
+                                     int m) {
+    return tab ? (R)tab[2 * m] : (R)(v.t_obs - ((gdouble *)st.times)[m]);
+}
+template <typename R>
+__device__ __forceinline__ R epoch_inv_dt(const StackDev &st, const ldsdouble *tab, int m) {
+    return tab ? (R)tab[2 * m + 1] : (R)((gdouble *)st.inv_dt)[m];
+}
 
 template <typename R>
 __device__ __forceinline__ void bracket_init(const RayView &v, const StackDev &st, bool lookback,
-                                             Bracket<R> &b) {
-    gdouble *t = (gdouble *)st.times, *idt = (gdouble *)st.inv_dt;
+                                             Bracket<R> &b, const ldsdouble *tab = nullptr) {
     const int M = st.n_epochs;
     b.m = lookback ? (M >= 2 ? M - 2 : 0) : v.fixed_m;
-    b.am = (R)(v.t_obs - t[b.m]);
-    b.am1 = M >= 2 ? (R)(v.t_obs - t[b.m + 1]) : b.am;
-    b.inv_dt = M >= 2 ? (R)idt[b.m] : (R)0;
+    b.am = epoch_a<R>(v, st, tab, b.m);
+    b.am1 = M >= 2 ? epoch_a<R>(v, st, tab, b.m + 1) : b.am;
+    b.inv_dt = M >= 2 ? epoch_inv_dt<R>(st, tab, b.m) : (R)0;
 }
 
 template <typename R>
 __device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &st, R mid,
-                                             Bracket<R> &b) {
-    gdouble *t = (gdouble *)st.times, *idt = (gdouble *)st.inv_dt;
+                                             Bracket<R> &b, const ldsdouble *tab = nullptr) {
     while (b.m > 0 && mid > b.am) {
         b.m--;
         b.am1 = b.am;
-        b.am = (R)(v.t_obs - t[b.m]);
-        b.inv_dt = (R)idt[b.m];
+        b.am = epoch_a<R>(v, st, tab, b.m);
+        b.inv_dt = epoch_inv_dt<R>(st, tab, b.m);
     }
 }
 
@@ -248,13 +277,12 @@ __device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &s
 // t_obs - s, so a piece that starts on an epoch time takes the earlier interval.
 template <typename R>
 __device__ __forceinline__ void bracket_seek_from(const RayView &v, const StackDev &st, R s,
-                                                  Bracket<R> &b) {
-    gdouble *t = (gdouble *)st.times, *idt = (gdouble *)st.inv_dt;
+                                                  Bracket<R> &b, const ldsdouble *tab = nullptr) {
     while (b.m > 0 && s >= b.am) {
         b.m--;
         b.am1 = b.am;
-        b.am = (R)(v.t_obs - t[b.m]);
-        b.inv_dt = (R)idt[b.m];
+        b.am = epoch_a<R>(v, st, tab, b.m);
+        b.inv_dt = epoch_inv_dt<R>(st, tab, b.m);
     }
 }
 
@@ -351,7 +379,7 @@ __device__ __forceinline__ R wave_min(R x) {
 template <int S, typename R, int SYNC, bool EX>
 __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                                         const double *centre, int pi, int pj, bool in_image,
-                                        uint32_t &nsteps) {
+                                        const ldsdouble *tab, uint32_t &nsteps) {
     using A = typename std::conditional<S == ST_F64, double, float>::type;
     using Raw = typename RecT<S>::raw;
     using GRaw = const Raw __attribute__((address_space(1)));
@@ -372,7 +400,7 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
     // only one epoch is used
     const int64_t second = single ? 0 : estride;
     Bracket<R> br;
-    bracket_init(v, st, lookback, br);
+    bracket_init(v, st, lookback, br, tab);
     GRaw *ebase = gdata + (int64_t)br.m * estride;  // records of epoch br.m
     int ebase_m = br.m;
     A sum = 0, comp = 0;
@@ -412,7 +440,7 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                     R b = a;
                     if (a < end) {
                         // bracket of the retarded times just below t_obs - a
-                        bracket_seek_from(v, st, a, br);
+                        bracket_seek_from(v, st, a, br, tab);
                         b = fmin(end, br.am);
                         more = b < end;
                     }
@@ -443,7 +471,7 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                     const bool contrib = ds > (R)0 && mid >= r_lo && mid <= r_hi;
                     R wt = (R)v.fixed_w;
                     if (lookback) {
-                        bracket_seek(v, st, mid, br);
+                        bracket_seek(v, st, mid, br, tab);
                         wt = (br.am - mid) * br.inv_dt;
                     }
                     if (br.m != ebase_m) {
@@ -506,17 +534,17 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
 // is uniform over the wavefront, as the depth-synchronous mode needs.
 template <int S, typename R, int SYNC, bool LAB, bool EX>
 __device__ __forceinline__ double pixel_value(const RayView &v, int pi, int pj, bool in_image,
-                                              uint32_t &nsteps) {
+                                              const ldsdouble *tab, uint32_t &nsteps) {
     // (labelled stacks get kernels of their own: the block loop would
     // otherwise raise the register count, and lower the occupancy, of every
     // plain render)
     if constexpr (!LAB) {
-        return march<S, R, SYNC, EX>(v, v.st, v.centre, pi, pj, in_image, nsteps);
+        return march<S, R, SYNC, EX>(v, v.st, v.centre, pi, pj, in_image, tab, nsteps);
     } else {
         double acc = 0.0;
         for (int b = 0; b < v.n_blocks; b++)
             acc += march<S, R, SYNC, EX>(v, v.blocks[b].st, v.blocks[b].centre, pi, pj,
-                                         in_image, nsteps);
+                                         in_image, tab, nsteps);
         return acc;
     }
 }
@@ -552,13 +580,19 @@ __device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, do
 template <int S, typename R, bool LAB, bool EX>
 __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
                                                unsigned long long *step_acc) {
+    __shared__ double s_tab[4][2 * EPOCH_TAB_MAX];
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long npix = (long long)v.width * v.height;
+    ldsdouble *tab = nullptr;
+    if (v.st.n_epochs <= EPOCH_TAB_MAX) {
+        tab = (ldsdouble *)&s_tab[threadIdx.x >> 6][0];
+        epoch_tab_fill(tab, v.st, v.t_obs);
+    }
     double val = 0.0;
     uint32_t ns = 0;
     if (idx < npix) {
         const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
-        val = pixel_value<S, R, 0, LAB, EX>(v, pi, pj, true, ns);
+        val = pixel_value<S, R, 0, LAB, EX>(v, pi, pj, true, tab, ns);
         store_pixel(v, pi, pj, val);
     }
     const double fs = wave_sum(val);
@@ -575,7 +609,15 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
 // round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
 // the other chunks when its own runs dry.
 template <int S, typename R, int SYNC, bool LAB, bool EX>
-__global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
+__global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
+                                               const RayView *__restrict__ views,
+                                               const Tile *__restrict__ tiles) {
+    // (descriptors through read-only, non-aliased pointers: uniform reads of
+    // them become scalar loads instead of round trips through the vector
+    // memory path that the gathers keep busy)
+    __shared__ double s_tab[4][2 * EPOCH_TAB_MAX];
+    ldsdouble *const wave_tab = (ldsdouble *)&s_tab[threadIdx.x >> 6][0];
+    uint32_t tab_view = 0xffffffffu;  // view whose epochs the table holds
     const int lane = threadIdx.x & 63;
     const uint32_t nq = bl.n_queues;
     const uint32_t q0 = blockIdx.x % nq;
@@ -590,9 +632,14 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
             qi++;
             continue;
         }
-        const Tile tile = bl.tiles[begin + t];
+        const Tile tile = tiles[begin + t];
         const uint32_t vi = __builtin_amdgcn_readfirstlane(tile.view);
-        const RayView &v = bl.views[vi];
+        const RayView &v = views[vi];
+        const bool use_tab = v.st.n_epochs <= EPOCH_TAB_MAX;
+        if (use_tab && vi != tab_view) {
+            epoch_tab_fill(wave_tab, v.st, v.t_obs);
+            tab_view = vi;
+        }
         const uint32_t tw_log2 = (uint32_t)__builtin_amdgcn_readfirstlane(v.tile_w_log2);
         const int pi = (int)(__builtin_amdgcn_readfirstlane(tile.tx) << tw_log2) +
                        (lane & ((1 << tw_log2) - 1));
@@ -600,7 +647,8 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
                        (lane >> tw_log2);
         uint32_t ns = 0;
         const bool in_image = pi < v.width && pj < v.height;
-        const double val = pixel_value<S, R, SYNC, LAB, EX>(v, pi, pj, in_image, ns);
+        const double val = pixel_value<S, R, SYNC, LAB, EX>(v, pi, pj, in_image,
+                                                            use_tab ? wave_tab : nullptr, ns);
         if (in_image) store_pixel(v, pi, pj, val);
         const double fs = wave_sum(val);
         const uint32_t cs = wave_sum_u32(ns);
@@ -767,14 +815,14 @@ template <int S, typename R>
 static hipError_t batch_impl(const BatchLaunch &bl, int variant, int grid_blocks, hipStream_t s) {
     const dim3 g((unsigned)grid_blocks), b(256);
     switch (variant & 7) {
-        case 0: hipLaunchKernelGGL((k_batch<S, R, 0, false, false>), g, b, 0, s, bl); break;
-        case 1: hipLaunchKernelGGL((k_batch<S, R, 1, false, false>), g, b, 0, s, bl); break;
-        case 2: hipLaunchKernelGGL((k_batch<S, R, 0, true, false>), g, b, 0, s, bl); break;
-        case 3: hipLaunchKernelGGL((k_batch<S, R, 1, true, false>), g, b, 0, s, bl); break;
-        case 4: hipLaunchKernelGGL((k_batch<S, R, 0, false, true>), g, b, 0, s, bl); break;
-        case 5: hipLaunchKernelGGL((k_batch<S, R, 1, false, true>), g, b, 0, s, bl); break;
-        case 6: hipLaunchKernelGGL((k_batch<S, R, 0, true, true>), g, b, 0, s, bl); break;
-        default: hipLaunchKernelGGL((k_batch<S, R, 1, true, true>), g, b, 0, s, bl); break;
+        case 0: hipLaunchKernelGGL((k_batch<S, R, 0, false, false>), g, b, 0, s, bl, bl.views, bl.tiles); break;
+        case 1: hipLaunchKernelGGL((k_batch<S, R, 1, false, false>), g, b, 0, s, bl, bl.views, bl.tiles); break;
+        case 2: hipLaunchKernelGGL((k_batch<S, R, 0, true, false>), g, b, 0, s, bl, bl.views, bl.tiles); break;
+        case 3: hipLaunchKernelGGL((k_batch<S, R, 1, true, false>), g, b, 0, s, bl, bl.views, bl.tiles); break;
+        case 4: hipLaunchKernelGGL((k_batch<S, R, 0, false, true>), g, b, 0, s, bl, bl.views, bl.tiles); break;
+        case 5: hipLaunchKernelGGL((k_batch<S, R, 1, false, true>), g, b, 0, s, bl, bl.views, bl.tiles); break;
+        case 6: hipLaunchKernelGGL((k_batch<S, R, 0, true, true>), g, b, 0, s, bl, bl.views, bl.tiles); break;
+        default: hipLaunchKernelGGL((k_batch<S, R, 1, true, true>), g, b, 0, s, bl, bl.views, bl.tiles); break;
     }
     return hipGetLastError();
 }

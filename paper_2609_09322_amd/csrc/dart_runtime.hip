@@ -702,7 +702,7 @@ static dart_status check_tuning(const dart_tuning *t) {
                     t->tile_h);
     if (t->waves_per_cu < 4 || t->waves_per_cu > 64 || t->waves_per_cu % 4)
         return fail(DART_E_INVAL, "waves_per_cu must be a multiple of 4 in [4, 64]");
-    if (t->order < 0 || t->order > 2) return fail(DART_E_INVAL, "order must be 0, 1 or 2");
+    if (t->order < 0 || t->order > 3) return fail(DART_E_INVAL, "order must be 0, 1, 2 or 3");
     if (t->orient != 0 && t->orient != 1) return fail(DART_E_INVAL, "orient must be 0 or 1");
     if (t->depth_sync < 0 || t->depth_sync > 64)
         return fail(DART_E_INVAL, "depth_sync must be in [0, 64]");
@@ -815,7 +815,23 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             }
     }
     for (Group &g : groups) {
-        if (tun.order == 2) {
+        if (tun.order == 3) {
+            // rows from the middle outward: the upper half from its last row
+            // up, then the lower half down.  Rows stay whole and in sequence
+            // (neighbouring tiles still run together), but the rows through
+            // the middle of the grid, whose rays are longest, start first and
+            // each queue chunk ends with short or empty rows.
+            auto row_key = [&g](const Tile &t) {
+                const RayView &tv = g.views[t.view];
+                const int th = 64 >> tv.tile_w_log2;
+                const int nty = (tv.height + th - 1) / th, half = nty / 2;
+                return t.ty < half ? half - 1 - t.ty : t.ty;
+            };
+            std::stable_sort(g.tiles.begin(), g.tiles.end(), [&](const Tile &a, const Tile &b) {
+                if (a.view != b.view) return a.view < b.view;
+                return row_key(a) < row_key(b);
+            });
+        } else if (tun.order == 2) {
             // Z-order (Morton) of the tile coordinates inside each view: tiles
             // that are close in the queue form compact 2D patches
             auto morton = [](uint32_t x, uint32_t y) {
@@ -1085,7 +1101,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
     // so the sweep covers low occupancies, row-like tiles and both spatial orders.
     const int shapes[][2] = {{64, 1}, {32, 2}, {16, 4}, {8, 8}};
     const int waves[] = {12, 16, 8};  // (ties go to the earliest: 12 first)
-    const int orders[] = {0, 1, 2};
+    const int orders[] = {0, 3, 1, 2};
     for (auto &sh : shapes)
         for (int w : waves)
             for (int order : orders)

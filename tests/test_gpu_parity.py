@@ -132,6 +132,20 @@ def test_batch_equals_plain_and_oracle(dart, store, sync):
                              saved.orient, saved.depth_sync)
 
 
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_tile_orders_keep_pixels(dart, order):
+    """Every tile queue order (longest first, Z-order, rows from the middle
+    outward) gives the plain kernel's pixels bit for bit."""
+    import torch
+    saved = dart.dart_get_tuning()
+    dart.dart_set_tuning(16, 4, 8, order, 1, 0)
+    try:
+        _batch_equals_plain_and_oracle(dart, "f32", torch)
+    finally:
+        dart.dart_set_tuning(saved.tile_w, saved.tile_h, saved.waves_per_cu, saved.order,
+                             saved.orient, saved.depth_sync)
+
+
 def _batch_equals_plain_and_oracle(dart, store, torch):
     dims_a, dims_b = (24, 20, 28), (16, 16, 16)
     ja, ba, ta = synth.random_stack(dims_a, 5, seed=1, beta_max=0.8)
