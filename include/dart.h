@@ -268,7 +268,8 @@ typedef struct {
     int32_t order;           /* tile queue order: 0 row-major, 1 longest estimated tile
                                 first, 2 Z-order (Morton), 3 rows from the image's middle
                                 outward (the upper half upward, then the lower half
-                                downward) */
+                                downward), 4 whole rows, longest first, dealt round
+                                robin to the per-XCD queues */
     int32_t orient;          /* 1: per view, turn the tile so that its long side follows
                                 the image-plane projection of the bricks' long axis
                                 (lanes of a wavefront then share cache lines) */

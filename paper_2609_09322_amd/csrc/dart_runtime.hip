@@ -702,7 +702,7 @@ static dart_status check_tuning(const dart_tuning *t) {
                     t->tile_h);
     if (t->waves_per_cu < 4 || t->waves_per_cu > 64 || t->waves_per_cu % 4)
         return fail(DART_E_INVAL, "waves_per_cu must be a multiple of 4 in [4, 64]");
-    if (t->order < 0 || t->order > 3) return fail(DART_E_INVAL, "order must be 0, 1, 2 or 3");
+    if (t->order < 0 || t->order > 4) return fail(DART_E_INVAL, "order must be in [0, 4]");
     if (t->orient != 0 && t->orient != 1) return fail(DART_E_INVAL, "orient must be 0 or 1");
     if (t->depth_sync < 0 || t->depth_sync > 64)
         return fail(DART_E_INVAL, "depth_sync must be in [0, 64]");
@@ -815,7 +815,43 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             }
     }
     for (Group &g : groups) {
-        if (tun.order == 3) {
+        if (tun.order == 4) {
+            // whole tile rows, the row with the longest estimated tile first,
+            // dealt round robin to the queue chunks: every chunk starts on
+            // heavy rows and ends on light ones, and a row's tiles stay
+            // together
+            struct Row { double cost; uint32_t view; uint16_t ty; std::vector<Tile> tiles; };
+            std::vector<Row> rows;
+            std::map<std::pair<uint32_t, uint16_t>, size_t> at;
+            for (const Tile &t : g.tiles) {
+                auto key = std::make_pair(t.view, t.ty);
+                auto it = at.find(key);
+                if (it == at.end()) {
+                    it = at.emplace(key, rows.size()).first;
+                    rows.push_back(Row{0.0, t.view, t.ty, {}});
+                }
+                const RayView &tv = g.views[t.view];
+                Row &r = rows[it->second];
+                r.cost = std::max(r.cost, tile_cost(tv, t.tx, t.ty, 1 << tv.tile_w_log2,
+                                                    64 >> tv.tile_w_log2));
+                r.tiles.push_back(t);
+            }
+            std::stable_sort(rows.begin(), rows.end(),
+                             [](const Row &a, const Row &b) { return a.cost > b.cost; });
+            const size_t nq = 8;
+            std::vector<std::vector<Tile>> chunk(nq);
+            std::vector<size_t> load(nq, 0);
+            for (const Row &r : rows) {
+                // the chunk with the fewest tiles so far (ties: the lowest index)
+                size_t q = 0;
+                for (size_t k = 1; k < nq; k++)
+                    if (load[k] < load[q]) q = k;
+                chunk[q].insert(chunk[q].end(), r.tiles.begin(), r.tiles.end());
+                load[q] += r.tiles.size();
+            }
+            g.tiles.clear();
+            for (const auto &c : chunk) g.tiles.insert(g.tiles.end(), c.begin(), c.end());
+        } else if (tun.order == 3) {
             // rows from the middle outward: the upper half from its last row
             // up, then the lower half down.  Rows stay whole and in sequence
             // (neighbouring tiles still run together), but the rows through
@@ -1101,7 +1137,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
     // so the sweep covers low occupancies, row-like tiles and both spatial orders.
     const int shapes[][2] = {{64, 1}, {32, 2}, {16, 4}, {8, 8}};
     const int waves[] = {12, 16, 8};  // (ties go to the earliest: 12 first)
-    const int orders[] = {0, 3, 1, 2};
+    const int orders[] = {0, 3, 1, 2, 4};
     for (auto &sh : shapes)
         for (int w : waves)
             for (int order : orders)

@@ -132,10 +132,11 @@ def test_batch_equals_plain_and_oracle(dart, store, sync):
                              saved.orient, saved.depth_sync)
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_tile_orders_keep_pixels(dart, order):
     """Every tile queue order (longest first, Z-order, rows from the middle
-    outward) gives the plain kernel's pixels bit for bit."""
+    outward, heavy rows dealt to the queues) gives the plain kernel's pixels
+    bit for bit."""
     import torch
     saved = dart.dart_get_tuning()
     dart.dart_set_tuning(16, 4, 8, order, 1, 0)
