@@ -54,29 +54,32 @@ def kernel_source_id():
 
 def tuning_key(t):
     """The --tuning string of a launch shape: tile_w,tile_h,waves_per_cu,order,
-    orient,brick_x,brick_y,brick_z,depth_sync."""
+    orient,brick_x,brick_y,brick_z,depth_sync,cells_per_batch."""
     return ",".join(str(x) for x in (t["tile"][0], t["tile"][1], t["waves_per_cu"], t["order"],
-                                     t["orient"], *t["brick"], t.get("depth_sync", 0)))
+                                     t["orient"], *t["brick"], t.get("depth_sync", 0),
+                                     t.get("cells_per_batch", 4) or 4))
 
 
 def tuning_dict(best, info):
     return {"tile": [best.tile_w, best.tile_h], "waves_per_cu": best.waves_per_cu,
             "order": best.order, "orient": best.orient, "brick": list(info.brick),
-            "depth_sync": best.depth_sync}
+            "depth_sync": best.depth_sync, "cells_per_batch": best.cells_per_batch or 4}
 
 
 def apply_fixed_tuning(dart, st, spec, stream):
     f = normalise_tuning(spec)
-    tw, th_, w, order, orient, bx, by, bz, sync = [int(x) for x in f.split(",")]
+    tw, th_, w, order, orient, bx, by, bz, sync, k = [int(x) for x in f.split(",")]
     dart.dart_stack_rebrick(st, (bx, by, bz), stream)
-    dart.dart_set_tuning(tw, th_, w, order, orient, sync)
+    dart.dart_set_tuning(tw, th_, w, order, orient, sync, k)
     return {"tile": [tw, th_], "waves_per_cu": w, "order": order, "orient": orient,
-            "brick": [bx, by, bz], "depth_sync": sync, "fixed": True}
+            "brick": [bx, by, bz], "depth_sync": sync, "cells_per_batch": k, "fixed": True}
 
 
 def normalise_tuning(spec):
-    """--tuning with the optional depth_sync field filled in (0)."""
-    return spec + ",0" if spec.count(",") == 7 else spec
+    """--tuning with the optional depth_sync (0) and cells_per_batch (4) fields
+    filled in."""
+    n = spec.count(",")
+    return spec + (",0,4" if n == 7 else ",4" if n == 8 else "")
 
 
 def measured_traffic(workload, tuning):
@@ -762,7 +765,7 @@ def run_labelled_workload(args, dart, torch):
     stream = torch.cuda.Stream()
     if args.tuning:
         f = [int(x) for x in normalise_tuning(args.tuning).split(",")]
-        dart.dart_set_tuning(f[0], f[1], f[2], f[3], f[4], f[8])
+        dart.dart_set_tuning(f[0], f[1], f[2], f[3], f[4], f[8], f[9])
         best = dart.dart_get_tuning()
     else:
         best, _ = dart.dart_autotune([lab] * 4, views, rebrick=False, stream=stream)

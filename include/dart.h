@@ -277,6 +277,10 @@ typedef struct {
                                 wavefront march together, no ray more than n cell
                                 lengths (largest cell side) ahead of the rearmost, so
                                 neighbouring rays read shared lines at the same time */
+    int32_t cells_per_batch; /* cells a lane walks before it requests their records in one
+                                go: 4 or 8 (0 means 4).  More cells keep more loads in
+                                flight per wavefront and cost registers; the pixels do
+                                not depend on it */
 } dart_tuning;
 
 /* Times the batched kernel on the given views over candidate tile shapes,

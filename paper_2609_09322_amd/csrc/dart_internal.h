@@ -88,8 +88,9 @@ struct BatchLaunch {
 hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *step_acc,
                         hipStream_t s);
 // Kernel variant bits: 1 depth-synchronous wavefronts, 2 the launch's views are
-// labelled stacks (block loop), 4 exact temporal integration.
-enum : int { KV_SYNC = 1, KV_LABELLED = 2, KV_EXACT = 4 };
+// labelled stacks (block loop), 4 exact temporal integration, 8 eight cells per
+// batch (else four).
+enum : int { KV_SYNC = 1, KV_LABELLED = 2, KV_EXACT = 4, KV_K8 = 8 };
 hipError_t launch_batch(int store, bool f64_dda, int variant, const BatchLaunch &bl,
                         int grid_blocks, hipStream_t s);
 hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s);

@@ -341,12 +341,10 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
     }
 }
 
-// Cells walked per batch: a lane walks CELLS_PER_BATCH cells of its ray, then
-// issues all their record loads back to back, then consumes them.
-#ifndef DART_CELLS_PER_BATCH
-#define DART_CELLS_PER_BATCH 4
-#endif
-constexpr int CELLS_PER_BATCH = DART_CELLS_PER_BATCH;
+// Cells walked per batch (K): a lane walks K cells of its ray, then issues all
+// their record loads back to back, then consumes them.  The batched kernel
+// comes with K = 4 and K = 8 (a tuning choice); the plain kernel uses 4.
+constexpr int CELLS_PER_BATCH = 4;
 
 // Marches pixel (pi, pj) of view v and returns its intensity (FP64 for the
 // caller's reductions); adds the counted cell-steps to nsteps.
@@ -376,14 +374,13 @@ __device__ __forceinline__ R wave_min(R x) {
 // so the midpoint value times the piece is its exact integral.  A batch slot
 // then takes one piece instead of one cell; a cell counts as one cell-step.
 // (Linear interpolation with lookback only: the host clears EX otherwise.)
-template <int S, typename R, int SYNC, bool EX>
+template <int S, typename R, int SYNC, bool EX, int K>
 __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                                         const double *centre, int pi, int pj, bool in_image,
                                         const ldsdouble *tab, uint32_t &nsteps) {
     using A = typename std::conditional<S == ST_F64, double, float>::type;
     using Raw = typename RecT<S>::raw;
     using GRaw = const Raw __attribute__((address_space(1)));
-    constexpr int K = CELLS_PER_BATCH;
     Ray<R> r;
     bool alive = in_image && ray_setup(v, st, centre, pi, pj, r);
     if (SYNC == 0 && !alive) return 0.0;
@@ -532,18 +529,18 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
 // stack (LAB), one march through each of its sub-domains in order, summed
 // (emission adds along the ray; sub-domains do not overlap).  The block loop
 // is uniform over the wavefront, as the depth-synchronous mode needs.
-template <int S, typename R, int SYNC, bool LAB, bool EX>
+template <int S, typename R, int SYNC, bool LAB, bool EX, int K>
 __device__ __forceinline__ double pixel_value(const RayView &v, int pi, int pj, bool in_image,
                                               const ldsdouble *tab, uint32_t &nsteps) {
     // (labelled stacks get kernels of their own: the block loop would
     // otherwise raise the register count, and lower the occupancy, of every
     // plain render)
     if constexpr (!LAB) {
-        return march<S, R, SYNC, EX>(v, v.st, v.centre, pi, pj, in_image, tab, nsteps);
+        return march<S, R, SYNC, EX, K>(v, v.st, v.centre, pi, pj, in_image, tab, nsteps);
     } else {
         double acc = 0.0;
         for (int b = 0; b < v.n_blocks; b++)
-            acc += march<S, R, SYNC, EX>(v, v.blocks[b].st, v.blocks[b].centre, pi, pj,
+            acc += march<S, R, SYNC, EX, K>(v, v.blocks[b].st, v.blocks[b].centre, pi, pj,
                                          in_image, tab, nsteps);
         return acc;
     }
@@ -592,7 +589,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
     uint32_t ns = 0;
     if (idx < npix) {
         const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
-        val = pixel_value<S, R, 0, LAB, EX>(v, pi, pj, true, tab, ns);
+        val = pixel_value<S, R, 0, LAB, EX, CELLS_PER_BATCH>(v, pi, pj, true, tab, ns);
         store_pixel(v, pi, pj, val);
     }
     const double fs = wave_sum(val);
@@ -608,7 +605,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
 // chunks; a wave starts on chunk (block index mod n_queues), which under
 // round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
 // the other chunks when its own runs dry.
-template <int S, typename R, int SYNC, bool LAB, bool EX>
+template <int S, typename R, int SYNC, bool LAB, bool EX, int K>
 __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
                                                const RayView *__restrict__ views,
                                                const Tile *__restrict__ tiles) {
@@ -647,7 +644,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
                        (lane >> tw_log2);
         uint32_t ns = 0;
         const bool in_image = pi < v.width && pj < v.height;
-        const double val = pixel_value<S, R, SYNC, LAB, EX>(v, pi, pj, in_image,
+        const double val = pixel_value<S, R, SYNC, LAB, EX, K>(v, pi, pj, in_image,
                                                             use_tab ? wave_tab : nullptr, ns);
         if (in_image) store_pixel(v, pi, pj, val);
         const double fs = wave_sum(val);
@@ -811,18 +808,27 @@ hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *
     return hipErrorInvalidValue;
 }
 
+template <int S, typename R, int SYNC, bool LAB, bool EX>
+static void batch_launch_k(const BatchLaunch &bl, bool k8, int grid_blocks, hipStream_t s) {
+    const dim3 g((unsigned)grid_blocks), b(256);
+    if (k8)
+        hipLaunchKernelGGL((k_batch<S, R, SYNC, LAB, EX, 8>), g, b, 0, s, bl, bl.views, bl.tiles);
+    else
+        hipLaunchKernelGGL((k_batch<S, R, SYNC, LAB, EX, 4>), g, b, 0, s, bl, bl.views, bl.tiles);
+}
+
 template <int S, typename R>
 static hipError_t batch_impl(const BatchLaunch &bl, int variant, int grid_blocks, hipStream_t s) {
-    const dim3 g((unsigned)grid_blocks), b(256);
+    const bool k8 = (variant & KV_K8) != 0;
     switch (variant & 7) {
-        case 0: hipLaunchKernelGGL((k_batch<S, R, 0, false, false>), g, b, 0, s, bl, bl.views, bl.tiles); break;
-        case 1: hipLaunchKernelGGL((k_batch<S, R, 1, false, false>), g, b, 0, s, bl, bl.views, bl.tiles); break;
-        case 2: hipLaunchKernelGGL((k_batch<S, R, 0, true, false>), g, b, 0, s, bl, bl.views, bl.tiles); break;
-        case 3: hipLaunchKernelGGL((k_batch<S, R, 1, true, false>), g, b, 0, s, bl, bl.views, bl.tiles); break;
-        case 4: hipLaunchKernelGGL((k_batch<S, R, 0, false, true>), g, b, 0, s, bl, bl.views, bl.tiles); break;
-        case 5: hipLaunchKernelGGL((k_batch<S, R, 1, false, true>), g, b, 0, s, bl, bl.views, bl.tiles); break;
-        case 6: hipLaunchKernelGGL((k_batch<S, R, 0, true, true>), g, b, 0, s, bl, bl.views, bl.tiles); break;
-        default: hipLaunchKernelGGL((k_batch<S, R, 1, true, true>), g, b, 0, s, bl, bl.views, bl.tiles); break;
+        case 0: batch_launch_k<S, R, 0, false, false>(bl, k8, grid_blocks, s); break;
+        case 1: batch_launch_k<S, R, 1, false, false>(bl, k8, grid_blocks, s); break;
+        case 2: batch_launch_k<S, R, 0, true, false>(bl, k8, grid_blocks, s); break;
+        case 3: batch_launch_k<S, R, 1, true, false>(bl, k8, grid_blocks, s); break;
+        case 4: batch_launch_k<S, R, 0, false, true>(bl, k8, grid_blocks, s); break;
+        case 5: batch_launch_k<S, R, 1, false, true>(bl, k8, grid_blocks, s); break;
+        case 6: batch_launch_k<S, R, 0, true, true>(bl, k8, grid_blocks, s); break;
+        default: batch_launch_k<S, R, 1, true, true>(bl, k8, grid_blocks, s); break;
     }
     return hipGetLastError();
 }

@@ -19,7 +19,7 @@ struct dart_stack {
     uint64_t bytes = 0;
     uint64_t generation = 0;  // bumped whenever the resident layout or data change
     int device = 0;
-    dart_tuning tuning{32, 2, 8, 0, 1, 0};
+    dart_tuning tuning{32, 2, 8, 0, 1, 0, 4};
     bool placed = false;               // set by dart_stack_set_placement
     double origin[3] = {0, 0, 0}, centre[3] = {0, 0, 0};
     bool tuned = false;

@@ -692,7 +692,7 @@ extern "C" dart_status dart_render(const dart_stack *s, const dart_view *v, void
 // ------------------------------------------------------------------ tuning
 
 static std::mutex g_tune_mu;
-static dart_tuning g_tuning = {32, 2, 8, 0, 1, 0};
+static dart_tuning g_tuning = {32, 2, 8, 0, 1, 0, 4};
 
 static dart_status check_tuning(const dart_tuning *t) {
     if (!t) return fail(DART_E_INVAL, "tuning is NULL");
@@ -706,6 +706,8 @@ static dart_status check_tuning(const dart_tuning *t) {
     if (t->orient != 0 && t->orient != 1) return fail(DART_E_INVAL, "orient must be 0 or 1");
     if (t->depth_sync < 0 || t->depth_sync > 64)
         return fail(DART_E_INVAL, "depth_sync must be in [0, 64]");
+    if (t->cells_per_batch != 0 && t->cells_per_batch != 4 && t->cells_per_batch != 8)
+        return fail(DART_E_INVAL, "cells_per_batch must be 4 or 8 (0 means 4)");
 
     return DART_OK;
 }
@@ -937,7 +939,7 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
         bl.flux_acc = (double *)acc;
         bl.step_acc = acc + n;
         const int variant = (tun.depth_sync > 0 ? KV_SYNC : 0) | (g.labelled ? KV_LABELLED : 0) |
-                            (g.exact ? KV_EXACT : 0);
+                            (g.exact ? KV_EXACT : 0) | (tun.cells_per_batch == 8 ? KV_K8 : 0);
         e = launch_batch(g.store, g.f64, variant, bl, blocks, stream);
         if (e != hipSuccess) return e;
     }
@@ -1255,14 +1257,18 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
             best_ms = cand_ms[k];
         }
     }
-    // Stage 3: depth-synchronous marching on the chosen launch shape.
+    // Stage 3: cells per batch and depth-synchronous marching on the chosen
+    // launch shape.
     if (result == DART_OK) {
         std::vector<dart_tuning> c3;
         std::vector<float> c3_ms;
         c3.push_back(best);
         c3_ms.push_back((float)best_ms);
-        for (int gap : {1, 2, 3, 4, 6}) {
+        for (int k : {4, 8})
+        for (int gap : {0, 1, 2, 3, 4, 6}) {
+            if (k == 4 && gap == 0) continue;  // the launch shape as chosen
             dart_tuning c = best;
+            c.cells_per_batch = k;
             c.depth_sync = gap;
             float ms = 0;
             result = measure(c, &ms);

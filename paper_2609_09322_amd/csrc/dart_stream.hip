@@ -404,7 +404,8 @@ extern "C" dart_status dart_streamer_render(dart_streamer *s, dart_dtype src_dty
             bl.n_queues = g.n_queues;
             bl.flux_acc = (double *)s->acc;
             bl.step_acc = s->acc + n;
-            const int variant = (tun.depth_sync > 0 ? KV_SYNC : 0) | (g.labelled ? KV_LABELLED : 0);
+            const int variant = (tun.depth_sync > 0 ? KV_SYNC : 0) | (g.labelled ? KV_LABELLED : 0) |
+                                (tun.cells_per_batch == 8 ? KV_K8 : 0);
             ST_TRY(launch_batch(g.store, g.f64, variant, bl, blocks, stream), "interval kernel");
         }
         for (int32_t e : {m, hi})

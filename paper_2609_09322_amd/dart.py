@@ -63,7 +63,8 @@ class dart_stack_info(ctypes.Structure):
 class dart_tuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("orient", ctypes.c_int32), ("depth_sync", ctypes.c_int32)]
+                ("orient", ctypes.c_int32), ("depth_sync", ctypes.c_int32),
+                ("cells_per_batch", ctypes.c_int32)]
 
 
 class dart_server_stats(ctypes.Structure):
@@ -330,8 +331,9 @@ def dart_autotune(stacks, views, rebrick=False, stream=None):
     return best, ms.value
 
 
-def dart_set_tuning(tile_w, tile_h, waves_per_cu, order=0, orient=1, depth_sync=0):
-    t = dart_tuning(tile_w, tile_h, waves_per_cu, order, orient, depth_sync)
+def dart_set_tuning(tile_w, tile_h, waves_per_cu, order=0, orient=1, depth_sync=0,
+                    cells_per_batch=4):
+    t = dart_tuning(tile_w, tile_h, waves_per_cu, order, orient, depth_sync, cells_per_batch)
     _check(_load().dart_set_tuning(ctypes.byref(t)))
 
 

@@ -78,7 +78,7 @@ def test_structs_match_header_layout():
     import paper_2609_09322_amd as d
     # dart_view: 2 doubles, 2 int32, 3 doubles, uint32 flags, 4-byte enum -> 56 bytes
     assert ctypes.sizeof(d.dart_view) == 56
-    assert ctypes.sizeof(d.dart_tuning) == 24
+    assert ctypes.sizeof(d.dart_tuning) == 28
     assert ctypes.sizeof(d.dart.dart_stream_stats) == 24
 
 

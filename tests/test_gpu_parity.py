@@ -132,6 +132,22 @@ def test_batch_equals_plain_and_oracle(dart, store, sync):
                              saved.orient, saved.depth_sync)
 
 
+@pytest.mark.parametrize("sync", [0, 2])
+def test_eight_cells_per_batch_keeps_pixels(dart, sync):
+    """Walking 8 cells per batch instead of 4 changes when records are
+    requested, not what is summed: the plain kernel's pixels bit for bit."""
+    import torch
+    saved = dart.dart_get_tuning()
+    dart.dart_set_tuning(32, 2, 8, 3, 1, sync, 8)
+    try:
+        assert dart.dart_get_tuning().cells_per_batch == 8
+        for store in ("f32", "f16"):
+            _batch_equals_plain_and_oracle(dart, store, torch)
+    finally:
+        dart.dart_set_tuning(saved.tile_w, saved.tile_h, saved.waves_per_cu, saved.order,
+                             saved.orient, saved.depth_sync, saved.cells_per_batch or 4)
+
+
 @pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_tile_orders_keep_pixels(dart, order):
     """Every tile queue order (longest first, Z-order, rows from the middle
