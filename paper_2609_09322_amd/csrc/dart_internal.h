@@ -73,13 +73,16 @@ struct Tile {
     uint16_t tx, ty;
 };
 
+constexpr int MAX_QUEUES = 8;
+
 // Launch parameters of the persistent batched kernel.
 struct BatchLaunch {
     const RayView *views;
     const Tile *tiles;
     uint32_t n_tiles;
     uint32_t *head;         // tile queue heads, one per XCD queue
-    uint32_t n_queues;
+    uint32_t n_queues;      // at most MAX_QUEUES
+    uint32_t q_begin[9];    // queue q holds tiles [q_begin[q], q_begin[q + 1])
     double *flux_acc;
     unsigned long long *step_acc;
 };

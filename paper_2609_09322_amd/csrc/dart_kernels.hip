@@ -602,7 +602,8 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
 
 // Persistent kernel: every wavefront pulls 64-pixel tiles (tile_w x tile_h)
 // from a queue until all are done.  Tiles are split into n_queues contiguous
-// chunks; a wave starts on chunk (block index mod n_queues), which under
+// chunks (bounds from the planner); a wave starts on chunk (block index mod
+// n_queues), which under
 // round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
 // the other chunks when its own runs dry.
 template <int S, typename R, int SYNC, bool LAB, bool EX, int K>
@@ -620,8 +621,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
     const uint32_t q0 = blockIdx.x % nq;
     for (uint32_t qi = 0; qi < nq;) {
         const uint32_t q = (q0 + qi) % nq;
-        const uint32_t begin = (uint32_t)(((uint64_t)bl.n_tiles * q) / nq);
-        const uint32_t end = (uint32_t)(((uint64_t)bl.n_tiles * (q + 1)) / nq);
+        const uint32_t begin = bl.q_begin[q], end = bl.q_begin[q + 1];
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(&bl.head[q], 1u);
         t = __builtin_amdgcn_readfirstlane(t);

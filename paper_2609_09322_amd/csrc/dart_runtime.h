@@ -56,6 +56,7 @@ struct Group {
     std::vector<Tile> tiles;
     size_t view_off = 0, tile_off = 0;  // offsets in the uploaded descriptor arrays
     uint32_t n_queues = 8;
+    uint32_t q_begin[MAX_QUEUES + 1] = {};  // chunk bounds in `tiles`
 };
 
 dart_status plan_batch(const dart_stack *const *stacks, const dart_view *views, int32_t n,

@@ -817,6 +817,8 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             }
     }
     for (Group &g : groups) {
+        const size_t nq = MAX_QUEUES;
+        bool bounds_set = false;
         if (tun.order == 4) {
             // whole tile rows, the row with the longest estimated tile first,
             // dealt round robin to the queue chunks: every chunk starts on
@@ -840,7 +842,6 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             }
             std::stable_sort(rows.begin(), rows.end(),
                              [](const Row &a, const Row &b) { return a.cost > b.cost; });
-            const size_t nq = 8;
             std::vector<std::vector<Tile>> chunk(nq);
             std::vector<size_t> load(nq, 0);
             for (const Row &r : rows) {
@@ -852,7 +853,12 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
                 load[q] += r.tiles.size();
             }
             g.tiles.clear();
-            for (const auto &c : chunk) g.tiles.insert(g.tiles.end(), c.begin(), c.end());
+            for (size_t q = 0; q < nq; q++) {
+                g.q_begin[q] = (uint32_t)g.tiles.size();
+                g.tiles.insert(g.tiles.end(), chunk[q].begin(), chunk[q].end());
+            }
+            g.q_begin[nq] = (uint32_t)g.tiles.size();
+            bounds_set = true;
         } else if (tun.order == 3) {
             // rows from the middle outward: the upper half from its last row
             // up, then the lower half down.  Rows stay whole and in sequence
@@ -895,7 +901,7 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             std::stable_sort(cost.begin(), cost.end(),
                              [](const std::pair<double, uint32_t> &a,
                                 const std::pair<double, uint32_t> &b) { return a.first > b.first; });
-            const size_t nt = g.tiles.size(), nq = 8;
+            const size_t nt = g.tiles.size();
             std::vector<Tile> out(nt);
             // rank r goes to chunk r % nq, position r / nq inside it
             std::vector<size_t> chunk_begin(nq + 1);
@@ -913,7 +919,10 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             }
             g.tiles.swap(out);
         }
-        g.n_queues = 8;
+        g.n_queues = (uint32_t)nq;
+        if (!bounds_set)
+            for (size_t q = 0; q <= nq; q++)
+                g.q_begin[q] = (uint32_t)(((uint64_t)g.tiles.size() * q) / nq);
     }
     return DART_OK;
 }
@@ -936,6 +945,7 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
         bl.n_tiles = (uint32_t)g.tiles.size();
         bl.head = (uint32_t *)(acc + 2 * (size_t)n + 4 * gi);
         bl.n_queues = g.n_queues;
+        for (uint32_t q = 0; q <= g.n_queues; q++) bl.q_begin[q] = g.q_begin[q];
         bl.flux_acc = (double *)acc;
         bl.step_acc = acc + n;
         const int variant = (tun.depth_sync > 0 ? KV_SYNC : 0) | (g.labelled ? KV_LABELLED : 0) |

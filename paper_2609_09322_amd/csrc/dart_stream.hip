@@ -402,6 +402,7 @@ extern "C" dart_status dart_streamer_render(dart_streamer *s, dart_dtype src_dty
             bl.n_tiles = (uint32_t)g.tiles.size();
             bl.head = (uint32_t *)(s->acc + 2 * (size_t)n + 4 * gi);
             bl.n_queues = g.n_queues;
+            for (uint32_t q = 0; q <= g.n_queues; q++) bl.q_begin[q] = g.q_begin[q];
             bl.flux_acc = (double *)s->acc;
             bl.step_acc = s->acc + n;
             const int variant = (tun.depth_sync > 0 ? KV_SYNC : 0) | (g.labelled ? KV_LABELLED : 0) |
