@@ -11,13 +11,20 @@
 #include "../../include/dart.h"
 #include "dart_internal.h"
 
+namespace dart {
+// Process-wide, never repeated: a stack created where a freed one lived, or
+// re-laid, never matches a cached plan of another.
+uint64_t next_generation();
+}  // namespace dart
+
 struct dart_stack {
     dart::StackDev dev{};
     dart_dtype storage = DART_F32;
     std::vector<double> times;
     std::vector<char> filled;
     uint64_t bytes = 0;
-    uint64_t generation = 0;  // bumped whenever the resident layout or data change
+    uint64_t generation = dart::next_generation();  // renewed whenever the resident layout
+                                                    // or data change
     int device = 0;
     dart_tuning tuning{32, 2, 8, 0, 1, 0, 4};
     bool placed = false;               // set by dart_stack_set_placement
@@ -82,6 +89,11 @@ struct Workspace {
     bool stage_ready = false;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint8_t> graph_key;
+    // the last batch plan (descriptors already on the device), replayed when
+    // the next call has the same key
+    std::vector<Group> plan_groups;
+    std::vector<uint8_t> plan_key;
+    bool plan_ready = false;
 };
 
 Workspace *get_workspace(hipStream_t stream);

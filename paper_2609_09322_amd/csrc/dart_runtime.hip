@@ -80,6 +80,11 @@ static int store_of(dart_dtype d) {
     }
     return -1;
 }
+uint64_t dart::next_generation() {
+    static std::atomic<uint64_t> counter{0};
+    return ++counter;
+}
+
 uint32_t dart::record_bytes(int store) {
     return store == ST_F64 ? 32u : store == ST_F32 ? 16u : 8u;
 }
@@ -241,7 +246,7 @@ static dart_status set_epochs_impl(dart_stack *s, int32_t m0, int32_t count, dar
                     (unsigned long long)z);
     }
     for (int32_t q = 0; q < count; q++) s->filled[m0 + q] = 1;
-    s->generation++;
+    s->generation = next_generation();
     return DART_OK;
 }
 
@@ -403,7 +408,7 @@ extern "C" dart_status dart_stack_set_placement(dart_stack *s, const double orig
         s->centre[a] = centre[a];
     }
     s->placed = true;
-    s->generation++;
+    s->generation = next_generation();
     return DART_OK;
 }
 
@@ -453,12 +458,12 @@ extern "C" dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3],
         // a failure part-way leaves epochs in mixed layouts: the stack is unusable
         if (e != hipSuccess) {
             for (int32_t m = 0; m < s->dev.n_epochs; m++) s->filled[m] = false;
-            s->generation++;
+            s->generation = next_generation();
             return hip_fail(e, "rebrick in place (the stack's epochs must be loaded again)");
         }
         tmp.dev.data = s->dev.data;
         s->dev = tmp.dev;
-        s->generation++;
+        s->generation = next_generation();
         return DART_OK;
     }
     HIP_TRY(em, "hipMalloc(rebrick)");
@@ -472,7 +477,7 @@ extern "C" dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3],
     (void)hipFree((void *)s->dev.data);
     s->dev = tmp.dev;
     s->bytes = bytes;
-    s->generation++;
+    s->generation = next_generation();
     return DART_OK;
 }
 
@@ -626,6 +631,9 @@ static void drop_graph(Workspace *ws) {
     if (ws->graph_exec) (void)hipGraphExecDestroy(ws->graph_exec);
     ws->graph_exec = nullptr;
     ws->graph_key.clear();
+    ws->plan_ready = false;
+    ws->plan_key.clear();
+    ws->plan_groups.clear();
 }
 
 hipError_t dart::ws_reserve(Workspace *ws, size_t n_views, size_t n_tiles, size_t img_bytes,
@@ -1041,7 +1049,11 @@ extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const 
             img_bytes += (b + 255) & ~(size_t)255;
         }
     }
-    const bool replay = ws->graph_exec && key == ws->graph_key && stream != nullptr;
+#ifndef DART_USE_GRAPH
+#define DART_USE_GRAPH 1
+#endif
+    const bool use_graph = DART_USE_GRAPH && stream != nullptr;
+    const bool replay = ws->plan_ready && key == ws->plan_key;
     if (!replay) {
         std::vector<Group> groups;
         // the plan needs image pointers; host ones are patched after reserve
@@ -1068,7 +1080,10 @@ extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const 
                 "H2D tiles");
         HIP_TRY(hipEventRecord(ws->stage_done, stream), "event");
         drop_graph(ws);
-        if (stream != nullptr) {
+        ws->plan_groups = groups;
+        ws->plan_key = key;
+        ws->plan_ready = true;
+        if (use_graph) {
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
             hipError_t e = enqueue_plan(groups, n, ws->acc, ws->views, ws->tiles, tun, ws->device, stream);
@@ -1084,12 +1099,14 @@ extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const 
             if (e != hipSuccess) return hip_fail(e, "instantiate graph");
             ws->graph_exec = exec;
             ws->graph_key = key;
-        } else {
-            HIP_TRY(enqueue_plan(groups, n, ws->acc, ws->views, ws->tiles, tun, ws->device, stream),
-                    "batch kernels");
         }
     }
-    if (ws->graph_exec && stream != nullptr) HIP_TRY(hipGraphLaunch(ws->graph_exec, stream), "graph launch");
+    if (use_graph && ws->graph_exec)
+        HIP_TRY(hipGraphLaunch(ws->graph_exec, stream), "graph launch");
+    else
+        HIP_TRY(enqueue_plan(ws->plan_groups, n, ws->acc, ws->views, ws->tiles, tun, ws->device,
+                             stream),
+                "batch kernels");
     for (int32_t i = 0; i < n; i++) note_use(stacks[i], stream);
     bool any_host = false;
     for (int32_t i = 0; i < n; i++) {

@@ -196,6 +196,31 @@ def _batch_equals_plain_and_oracle(dart, store, torch):
         assert pix_err(got, ref).max() <= TOL[store]
 
 
+@pytest.mark.parametrize("on_stream", [False, True])
+def test_replay_follows_a_new_stack(dart, on_stream):
+    """A batched call repeated with the same arguments replays its cached plan;
+    a stack freed and replaced (often at the same host address) must not be
+    taken for the old one: the images follow the new stack's data."""
+    import torch
+    dims = (20, 18, 22)
+    views = [dart.View(35.0, 40.0, 33, 27, 1.1 * synth.diag(dims) / 33, 0.0, 0.7)]
+    img = [torch.zeros((27, 33), dtype=torch.float32, device="cuda")]
+    stream = torch.cuda.Stream() if on_stream else None
+    for seed in (3, 4, 5):
+        j, b, t = synth.random_stack(dims, 4, seed=seed, beta_max=0.7,
+                                     times=np.linspace(-20.0, 20.0, 4))
+        st = dart.dart_load_epochs(dims, (1, 1, 1), t, j.astype(np.float32), b.astype(np.float32),
+                                   dart.DART_F32)
+        for _ in range(2):
+            dart.dart_render_batch([st], views, img, stream=stream)
+        torch.cuda.synchronize()
+        plain = np.zeros((27, 33), dtype=np.float32)
+        dart.dart_render(st, views[0], plain)
+        np.testing.assert_array_equal(img[0].cpu().numpy(), plain)
+        dart.dart_free_epochs(st)
+        del st
+
+
 def test_graph_replay_is_stable(dart):
     """Repeated identical batch calls replay a captured graph: every replay
     must reproduce the first result exactly."""
