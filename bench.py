@@ -14,8 +14,10 @@ same stack and views for comparison.
 
 Other workloads: ``batch`` (384^3, 32 epochs, FP16 or BF16, 64 isotropic views
 with sides from {128, 256, 512, 1024}), ``serve`` (Poisson request stream on
-resident 128^3..512^3 FP16 stacks) and ``large`` (512 x 512 x 2048, 40 epochs,
-BF16, 1024^2 views).
+resident 128^3..512^3 FP16 stacks), ``large`` (512 x 512 x 2048, 40 epochs,
+BF16, 1024^2 views), ``labelled`` (the jet with its core refined), ``stream``
+(the jet's epochs streamed from host memory) and ``vector`` (the jet with three
+emissivity components).
 
 Prints one JSON line (rank 0).
 """
@@ -824,6 +826,123 @@ def run_labelled_workload(args, dart, torch):
     }
 
 
+def run_vector_workload(args, dart, torch):
+    """Vector sums: the jet grid (256x256x512, 16 epochs, FP32) with three
+    components, a total emissivity I and two signed ones Q = 0.6 I cos(2 chi),
+    U = 0.6 I sin(2 chi) (chi: a synthetic angle field that winds around the
+    jet axis and twists along it), all with the jet's velocity; the four jet
+    views.  One fused render of the vector stack against the three components
+    rendered as scalar stacks in one batch."""
+    import synth
+    dims, M = (256, 256, 512), 16
+    t0 = time.time()
+    j, b, times = synth.jet_torch(dims, M, 2, gamma_spine=5.0, n_knots=4)
+    nx, ny, nz = dims
+    z = torch.arange(nz, device="cuda", dtype=torch.float32).view(nz, 1, 1)
+    y = torch.arange(ny, device="cuda", dtype=torch.float32).view(1, ny, 1)
+    x = torch.arange(nx, device="cuda", dtype=torch.float32).view(1, 1, nx)
+    chi = torch.atan2(y + 0.5 - 0.5 * ny, x + 0.5 - 0.5 * nx) + (z / nz) * math.pi
+    q = (0.6 * j * torch.cos(2.0 * chi)).contiguous()
+    u = (0.6 * j * torch.sin(2.0 * chi)).contiguous()
+    del chi
+    torch.cuda.synchronize()
+    comps = []
+    host = []
+    for arr in (j, q, u):
+        s = dart.dart_load_epochs(dims, (1.0, 1.0, 1.0), times, arr, b, dart.DART_F32)
+        torch.cuda.synchronize()
+        dart.dart_stack_rebrick(s, (1, 8, 1))
+        comps.append(s)
+        if args.check:
+            host.append(arr.cpu().numpy())
+    bh = b.cpu().numpy() if args.check else None
+    del j, q, u, b
+    torch.cuda.empty_cache()
+    vec = dart.dart_vector_create(comps)
+    gb = dart.dart_stack_get_info(vec).device_bytes / 1e9
+    log(f"vector stack: 3 components, {gb:.1f} GB, built in {time.time() - t0:.1f} s")
+    L = synth.diag(dims)
+    views = [dart.View(th, 0.0, 512, 512, L / 512, 0.0, 0.6) for th in (10.0, 30.0, 60.0, 90.0)]
+    stream = torch.cuda.Stream()
+    if args.tuning:
+        f = [int(x) for x in normalise_tuning(args.tuning).split(",")]
+        dart.dart_set_tuning(f[0], f[1], f[2], f[3], f[4], f[8], f[9])
+        best = dart.dart_get_tuning()
+    else:
+        best, _ = dart.dart_autotune([vec] * 4, views, rebrick=False, stream=stream)
+    tuning = tuning_dict(best, dart.dart_stack_get_info(comps[0]))
+    vimgs = [torch.zeros((3, 512, 512), dtype=torch.float32, device="cuda") for _ in views]
+    flux, steps = dart.dart_render_batch([vec] * 4, views, vimgs, stream=stream)
+    cell_steps = int(np.sum(steps))
+
+    def fused():
+        dart.dart_render_batch([vec] * 4, views, vimgs, stream=stream, stats=False)
+
+    wall, per = time_steps(torch, stream, fused, args.steps, args.warmup)
+    ms_step = 1e3 * wall / args.steps
+    kernel_ms = float(np.mean(per))
+    simgs = [torch.zeros((512, 512), dtype=torch.float32, device="cuda") for _ in range(12)]
+    sstacks = [c for c in comps for _ in views]
+    sviews = views * 3
+
+    def separate():
+        dart.dart_render_batch(sstacks, sviews, simgs, stream=stream, stats=False)
+
+    swall, _ = time_steps(torch, stream, separate, args.steps, args.warmup)
+    sms = 1e3 * swall / args.steps
+    torch.cuda.synchronize()
+    same = all(torch.equal(vimgs[k][c], simgs[c * 4 + k]) for c in range(3) for k in range(4))
+    samples = sum(dart.dart_count_samples(comps[0], v, stream) for v in views)
+    out_bytes = 3 * 4 * 512 * 512 * len(views)
+    # component 0's whole record and the emissivity field of the two others
+    compulsory = samples * (16 + 2 * 4) + out_bytes
+    achieved = compulsory / (kernel_ms * 1e-3) / 1e9
+    log(f"vector: fused {ms_step:.3f} ms/step, three scalar stacks {sms:.3f} ms/step, "
+        f"{cell_steps:.4e} cell-steps, identical {same}")
+    acc = None
+    if args.check:
+        import oracle
+        rng = np.random.default_rng(11)
+        errs = []
+        for c in range(3):
+            ost = oracle.Stack(host[c], bh, times, encoding="f32")
+            ost_abs = oracle.Stack(np.abs(host[c]), bh, times, encoding="f32")
+            for k, v in enumerate(views):
+                pix = np.stack([rng.integers(0, 512, 128), rng.integers(0, 512, 128)],
+                               axis=1).astype(np.int32)
+                ov = oracle.View(v.theta_deg, v.phi_deg, 512, 512, v.pixel_scale, 0.0, 0.6, 0)
+                ref, _ = oracle.render(ost, ov, pixels=pix)
+                scale, _ = oracle.render(ost_abs, ov, pixels=pix)
+                got = vimgs[k][c].cpu().numpy()[pix[:, 1], pix[:, 0]].astype(np.float64)
+                floor = 1e-3 * max(float(scale.max()), 1e-300)
+                errs.append(float((np.abs(got - ref) / np.maximum(scale, floor)).max()))
+        acc = {"max_pixel_rel_err": max(errs), "sampled_pixels": 128 * 4 * 3,
+               "tolerance": 1e-5, "definition": "|got - oracle| / oracle render of |j_c|"}
+        log(f"accuracy vs the oracle: {acc}")
+    return {
+        "metric": "cell-steps/s & images/s (batched vs plain kernel) at 1e-5 rel; p50/p99 ms",
+        "value": cell_steps / (ms_step * 1e-3), "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "vector: jet 256x256x512, 16 epochs, FP32, components I, Q, U, "
+                               "4 views 512^2", "components": 3, "resident_gb": gb,
+                   "cell_steps_per_step": cell_steps},
+        "component_cell_steps_per_s": 3 * cell_steps / (ms_step * 1e-3),
+        "images_per_s": 12 / (ms_step * 1e-3), "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
+        "separate": {"ms_per_step": sms, "note": "the three components as scalar stacks, 12 "
+                     "images in one batched call", "identical_to_fused": bool(same)},
+        "speedup_vs_separate": sms / ms_step,
+        "accuracy": acc, "tuning": tuning,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": compulsory,
+                     "bytes_definition": "distinct (cell, epoch) samples x (component 0's record "
+                                         "+ 4 B emissivity of each other component) + images"},
+        "cpu_baseline": None,
+    }
+
+
 def run_stream_workload(args, dart, torch):
     """Out-of-core: the jet epochs (256x256x512, 16 epochs, FP32 source) stay
     in pinned host memory (or, second measurement, in device memory in the
@@ -946,7 +1065,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="jet",
-                    choices=["jet", "batch", "serve", "large", "labelled", "stream"])
+                    choices=["jet", "batch", "serve", "large", "labelled", "stream", "vector"])
     ap.add_argument("--large-views", type=int, default=256)
     ap.add_argument("--large-check", type=int, default=4)
     ap.add_argument("--large-slabs", type=int, default=2,
@@ -1013,6 +1132,8 @@ def main():
         line = run_labelled_workload(args, dart, torch)
     elif args.workload == "stream":
         line = run_stream_workload(args, dart, torch)
+    elif args.workload == "vector":
+        line = run_vector_workload(args, dart, torch)
     else:
         line = run_large_workload(args, dart, torch)
     print(json.dumps(line), flush=True)

@@ -166,6 +166,31 @@ dart_status dart_stack_set_placement(dart_stack *s, const double origin[3], cons
  * return DART_E_INVAL for it.  n_blocks in [1, 65536]; on error *out = NULL. */
 dart_status dart_labelled_create(dart_stack *const *blocks, int32_t n_blocks, dart_stack **out);
 
+/* Vector sums (the line integral of Eq. 1 for a vector-valued emissivity, e.g.
+ * the Stokes components a polarised emitter would carry; the paper names
+ * polarisation as future work, Sec. 7): one stack made of n in [2, 4]
+ * component stacks with the same dims, cell size, brick shape, layout,
+ * placement, storage type, device and epoch times.  The emissivity of
+ * components 1.. is also kept packed (one value per cell and epoch, a quarter
+ * of the record bytes each), refreshed by the next render after a component's
+ * epochs are refilled; dart_stack_get_info counts it.  A render marches each ray
+ * once: the chords, epoch weights (Eqs. 6-7) and the Doppler factor D^p of
+ * component 0's velocity (Eq. 14) are applied to the emissivity of every
+ * component, each summed on its own as in Eq. 19.  The other components'
+ * velocities are not read (the caller gives them the same field; a rotation
+ * of the polarisation plane by aberration is not modelled).  Component c of
+ * pixel (i, j) equals the scalar render of (j_c, component 0's velocity).
+ * Images are [n][height][width] at the view's image pointer (host or device,
+ * as for one scalar image); flux and cell steps refer to component 0.
+ * dart_render, dart_render_batch (vector and scalar views mix freely) accept
+ * it; dart_submit, DART_EXACT_TIME, dart_labelled_create, dart_stack_rebrick,
+ * dart_stack_set_epochs, dart_stack_set_placement and dart_autotune with
+ * rebrick != 0 return DART_E_INVAL for it; batched renders of it march without
+ * depth sync.  The components stay owned by the caller and cannot be freed,
+ * re-laid or re-placed while the vector stack holds them (DART_E_BUSY); their
+ * epochs may be refilled.  Free it with dart_free_epochs.  On error *out = NULL. */
+dart_status dart_vector_create(dart_stack *const *components, int32_t n, dart_stack **out);
+
 /* Re-lays the resident stack with a new brick shape (powers of two, each
  * 1..16, at most 4096 cells per brick); the current shape returns at once.
  * Uses a second copy of the stack when device memory allows, else (when the

@@ -66,6 +66,12 @@ struct RayView {
     StackDev st;            // the stack (a labelled stack: its first sub-domain)
     const Block *blocks;    // labelled stack: its sub-domains (device), else null
     int32_t n_blocks;       // 0 for a plain stack
+    // vector stack: n_chan components (2..4) with the same grid and layout;
+    // st is component 0 (its velocity sets D for all), chan_data[c - 1] the
+    // emissivity of component c packed one value per record index.  Images
+    // are [n_chan][height][width].  n_chan = 1 otherwise.
+    int32_t n_chan;
+    const void *chan_data[3];
 };
 
 struct Tile {
@@ -92,8 +98,8 @@ hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *
                         hipStream_t s);
 // Kernel variant bits: 1 depth-synchronous wavefronts, 2 the launch's views are
 // labelled stacks (block loop), 4 exact temporal integration, 8 eight cells per
-// batch (else four).
-enum : int { KV_SYNC = 1, KV_LABELLED = 2, KV_EXACT = 4, KV_K8 = 8 };
+// batch (else four), 16 vector stacks (only alone: no other bit but 8).
+enum : int { KV_SYNC = 1, KV_LABELLED = 2, KV_EXACT = 4, KV_K8 = 8, KV_VEC = 16 };
 hipError_t launch_batch(int store, bool f64_dda, int variant, const BatchLaunch &bl,
                         int grid_blocks, hipStream_t s);
 hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s);
@@ -104,6 +110,8 @@ hipError_t launch_convert(int src_f64, int store, const void *j, const void *bet
                           unsigned long long *err, hipStream_t s);
 hipError_t launch_rebrick(int store, const StackDev &from, const StackDev &to, void *dst,
                           hipStream_t s);
+// Emissivity fields of n resident records into a packed array (vector stacks).
+hipError_t launch_pack_j(int store, const void *records, void *out, uint64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,
                            hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);

@@ -73,39 +73,65 @@ __device__ __forceinline__ void decode(const typename RecT<S>::raw &r, V &j, V &
     }
 }
 
-// D^p j of one record (Eq. 14 raised to p, times the rest-frame emissivity).
-// FP64 stacks: all in FP64.  FP32 stacks: 1 - beta^2 and 1 + beta.s in FP64
-// (the two quantities that cancel at high Lorentz factor), logs in FP32.
-// 16-bit stacks: FP32 FMA chains starting from 1, with s_hat split in two
-// floats: rounding s_hat to FP32 alone moves 1 + beta.s by ~6e-8 absolute,
-// which near the beaming peak (1 + beta.s ~ 0.05 at Lorentz factor 4) is a
-// systematic ~1e-6 relative error of D^p over the whole image.
+// D^p of one record (Eq. 14 raised to p), and its rest-frame emissivity in j.
 template <int S>
-__device__ __forceinline__ typename RecT<S>::val boosted(const typename RecT<S>::raw &r,
-                                                        const RayView &v, bool beaming) {
+__device__ __forceinline__ typename RecT<S>::val boost_factor(const typename RecT<S>::raw &r,
+                                                             const RayView &v, bool beaming,
+                                                             typename RecT<S>::val &j) {
     using V = typename RecT<S>::val;
-    V j, bx, by, bz;
+    V bx, by, bz;
     decode<S, V>(r, j, bx, by, bz);
-    if (!beaming || (bx == V(0) && by == V(0) && bz == V(0))) return j;
+    if (!beaming || (bx == V(0) && by == V(0) && bz == V(0))) return V(1);
     if constexpr (S == ST_F64) {
         double q = fma(-bx, bx, fma(-by, by, fma(-bz, bz, 1.0)));
         double rr = fma(bx, v.shat[0], fma(by, v.shat[1], fma(bz, v.shat[2], 1.0)));
-        return j * exp2(v.p * (0.5 * log2(q) - log2(rr)));
+        return exp2(v.p * (0.5 * log2(q) - log2(rr)));
     } else if constexpr (S == ST_F32) {
         double dx = bx, dy = by, dz = bz;
         double q = fma(-dx, dx, fma(-dy, dy, fma(-dz, dz, 1.0)));
         double rr = fma(dx, v.shat[0], fma(dy, v.shat[1], fma(dz, v.shat[2], 1.0)));
         float p = (float)v.p;
         float e = fmaf(0.5f * p, __builtin_amdgcn_logf((float)q), -p * __builtin_amdgcn_logf((float)rr));
-        return j * __builtin_amdgcn_exp2f(e);
+        return __builtin_amdgcn_exp2f(e);
     } else {
         float q = fmaf(-bx, bx, fmaf(-by, by, fmaf(-bz, bz, 1.0f)));
         float rr = fmaf(bx, v.shat_hi[0], fmaf(by, v.shat_hi[1], fmaf(bz, v.shat_hi[2], 1.0f)));
         rr += fmaf(bx, v.shat_lo[0], fmaf(by, v.shat_lo[1], bz * v.shat_lo[2]));
         float p = (float)v.p;
         float e = fmaf(0.5f * p, __builtin_amdgcn_logf(q), -p * __builtin_amdgcn_logf(rr));
-        return j * __builtin_amdgcn_exp2f(e);
+        return __builtin_amdgcn_exp2f(e);
     }
+}
+
+// Rest-frame emissivity times D^p of one record (Eq. 14 raised to p, times j).
+// FP64 stacks: all in FP64.  FP32 stacks: 1 - beta^2 and 1 + beta.s in FP64
+// (the two quantities that cancel at high Lorentz factor), logs in FP32.
+// 16-bit stacks: FP32 FMA chains starting from 1, with s_hat split in two
+// floats: rounding s_hat to FP32 alone moves 1 + beta.s by ~6e-8 absolute,
+// which near the beaming peak (1 + beta.s ~ 0.05 at Lorentz factor 4) is a
+// systematic ~1e-6 relative error of D^p over the whole image.  (The factor is
+// exactly 1 without beaming or at rest, and j * 1 is j.)
+template <int S>
+__device__ __forceinline__ typename RecT<S>::val boosted(const typename RecT<S>::raw &r,
+                                                        const RayView &v, bool beaming) {
+    typename RecT<S>::val j;
+    const typename RecT<S>::val f = boost_factor<S>(r, v, beaming, j);
+    return j * f;
+}
+
+// Emissivity of another component of a vector stack, packed one value per
+// (epoch, cell) in the stack's storage type at the record's index.
+template <int S> struct JFieldT;
+template <> struct JFieldT<ST_F64> { using raw = double; };
+template <> struct JFieldT<ST_F32> { using raw = float; };
+template <> struct JFieldT<ST_F16> { using raw = unsigned short; };
+template <> struct JFieldT<ST_BF16> { using raw = unsigned short; };
+
+template <int S>
+__device__ __forceinline__ typename RecT<S>::val decode_j(typename JFieldT<S>::raw w) {
+    if constexpr (S == ST_F64 || S == ST_F32) return w;
+    else if constexpr (S == ST_F16) return h2f((uint32_t)w);
+    else return __uint_as_float((uint32_t)w << 16);
 }
 
 // ------------------------------------------------------------------ one ray
@@ -374,13 +400,25 @@ __device__ __forceinline__ R wave_min(R x) {
 // so the midpoint value times the piece is its exact integral.  A batch slot
 // then takes one piece instead of one cell; a cell counts as one cell-step.
 // (Linear interpolation with lookback only: the host clears EX otherwise.)
-template <int S, typename R, int SYNC, bool EX, int K>
+// VEC (vector stacks): the same walk, weights and D^p also integrate the
+// emissivity of components 1..n_chan-1, each with its own compensated sum,
+// returned in ext[0..2].
+template <int S, typename R, int SYNC, bool EX, int K, bool VEC = false>
 __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                                         const double *centre, int pi, int pj, bool in_image,
-                                        const ldsdouble *tab, uint32_t &nsteps) {
+                                        const ldsdouble *tab, uint32_t &nsteps,
+                                        double *ext = nullptr) {
     using A = typename std::conditional<S == ST_F64, double, float>::type;
+    using V = typename RecT<S>::val;
     using Raw = typename RecT<S>::raw;
     using GRaw = const Raw __attribute__((address_space(1)));
+    using JF = typename JFieldT<S>::raw;
+    using GJ = const JF __attribute__((address_space(1)));
+    constexpr int NX = VEC ? 3 : 1;  // extra component slots
+    if constexpr (VEC) {
+#pragma unroll
+        for (int c = 0; c < NX; c++) ext[c] = 0.0;
+    }
     Ray<R> r;
     bool alive = in_image && ray_setup(v, st, centre, pi, pj, r);
     if (SYNC == 0 && !alive) return 0.0;
@@ -401,6 +439,10 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
     GRaw *ebase = gdata + (int64_t)br.m * estride;  // records of epoch br.m
     int ebase_m = br.m;
     A sum = 0, comp = 0;
+    A xsum[NX], xcomp[NX];
+#pragma unroll
+    for (int c = 0; c < NX; c++) xsum[c] = xcomp[c] = 0;
+    const int nx = VEC ? v.n_chan - 1 : 0;
     uint32_t count = 0;
     // a ray crosses at most n0 + n1 + n2 - 2 cells
     int budget = st.n[0] + st.n[1] + st.n[2] + 3;
@@ -494,10 +536,24 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
             }
         }
         Raw r0[K], r1[K];
+        JF j0[K][NX], j1[K][NX];
 #pragma unroll
         for (int k = 0; k < K; k++) {
             r0[k] = load_grec<S>(addr[k]);
             r1[k] = load_grec<S>(addr[k] + second);
+            if constexpr (VEC) {
+                // the same record index in the other components
+                const int64_t ri = addr[k] - gdata;
+#pragma unroll
+                for (int c = 0; c < NX; c++) {
+                    j0[k][c] = j1[k][c] = (JF)0;
+                    if (c < nx) {
+                        GJ *cd = (GJ *)v.chan_data[c];
+                        j0[k][c] = cd[ri];
+                        j1[k][c] = cd[ri + second];
+                    }
+                }
+            }
         }
         // Every lane consumes all K cells: a cell not taken, past the end of
         // the ray or outside the window has ds = 0 (its records, validated at
@@ -505,9 +561,38 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
         // sinking the loads back into a branch.
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            A val = (A)boosted<S>(r0[k], v, beaming);
-            const A b1 = (A)boosted<S>(r1[k], v, beaming);
+            V f0 = V(1), f1 = V(1);
+            A val, b1;
+            if constexpr (VEC) {
+                V jj0, jj1;
+                f0 = boost_factor<S>(r0[k], v, beaming, jj0);
+                f1 = boost_factor<S>(r1[k], v, beaming, jj1);
+                val = (A)(jj0 * f0);
+                b1 = (A)(jj1 * f1);
+            } else {
+                val = (A)boosted<S>(r0[k], v, beaming);
+                b1 = (A)boosted<S>(r1[k], v, beaming);
+            }
             val = val + cw[k] * (b1 - val);
+            if constexpr (VEC) {
+#pragma unroll
+                for (int c = 0; c < NX; c++) {
+                    if (c < nx) {
+                        A xv = (A)(decode_j<S>(j0[k][c]) * f0);
+                        const A xb = (A)(decode_j<S>(j1[k][c]) * f1);
+                        xv = xv + cw[k] * (xb - xv);
+                        const A xt = cds[k] * xv;
+                        if (kahan && xt != (A)0) {
+                            const A yk = xt - xcomp[c];
+                            const A tk = xsum[c] + yk;
+                            xcomp[c] = (tk - xsum[c]) - yk;
+                            xsum[c] = tk;
+                        } else {
+                            xsum[c] += xt;
+                        }
+                    }
+                }
+            }
             const A term = cds[k] * val;
             // a zero term leaves the compensated sum as it is, so cells not
             // taken in a batch do not perturb it (rounding of sum - comp)
@@ -522,6 +607,10 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
         }
     }
     nsteps += count;
+    if constexpr (VEC) {
+#pragma unroll
+        for (int c = 0; c < NX; c++) ext[c] = (double)xsum[c] - (double)xcomp[c];
+    }
     return (double)sum - (double)comp;
 }
 
@@ -529,14 +618,18 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
 // stack (LAB), one march through each of its sub-domains in order, summed
 // (emission adds along the ray; sub-domains do not overlap).  The block loop
 // is uniform over the wavefront, as the depth-synchronous mode needs.
-template <int S, typename R, int SYNC, bool LAB, bool EX, int K>
+// Vector stacks (VEC, never with LAB) also return components 1.. in ext.
+template <int S, typename R, int SYNC, bool LAB, bool EX, int K, bool VEC = false>
 __device__ __forceinline__ double pixel_value(const RayView &v, int pi, int pj, bool in_image,
-                                              const ldsdouble *tab, uint32_t &nsteps) {
+                                              const ldsdouble *tab, uint32_t &nsteps,
+                                              double *ext = nullptr) {
     // (labelled stacks get kernels of their own: the block loop would
     // otherwise raise the register count, and lower the occupancy, of every
     // plain render)
+    static_assert(!(LAB && VEC), "vector stacks are not labelled");
     if constexpr (!LAB) {
-        return march<S, R, SYNC, EX, K>(v, v.st, v.centre, pi, pj, in_image, tab, nsteps);
+        return march<S, R, SYNC, EX, K, VEC>(v, v.st, v.centre, pi, pj, in_image, tab, nsteps,
+                                             ext);
     } else {
         double acc = 0.0;
         for (int b = 0; b < v.n_blocks; b++)
@@ -559,8 +652,11 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
     return x;
 }
 
-__device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, double val) {
-    const size_t o = (size_t)pj * v.width + pi;
+// Pixel (pi, pj) of image plane c ([n_chan][height][width]; c = 0 for a
+// scalar stack).
+__device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, double val,
+                                            int c = 0) {
+    const size_t o = ((size_t)c * v.height + pj) * v.width + pi;
     const bool add = (v.flags & F_ACCUMULATE) != 0;
     if (v.out_f64) {
         double *p = (double *)v.image + o;
@@ -574,7 +670,7 @@ __device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, do
 // ------------------------------------------------------------------ kernels
 
 // Plain kernel: one thread per pixel in row order, one launch per image.
-template <int S, typename R, bool LAB, bool EX>
+template <int S, typename R, bool LAB, bool EX, bool VEC = false>
 __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
                                                unsigned long long *step_acc) {
     __shared__ double s_tab[4][2 * EPOCH_TAB_MAX];
@@ -589,8 +685,11 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
     uint32_t ns = 0;
     if (idx < npix) {
         const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
-        val = pixel_value<S, R, 0, LAB, EX, CELLS_PER_BATCH>(v, pi, pj, true, tab, ns);
+        double ext[3];
+        val = pixel_value<S, R, 0, LAB, EX, CELLS_PER_BATCH, VEC>(v, pi, pj, true, tab, ns, ext);
         store_pixel(v, pi, pj, val);
+        if constexpr (VEC)
+            for (int c = 1; c < v.n_chan; c++) store_pixel(v, pi, pj, ext[c - 1], c);
     }
     const double fs = wave_sum(val);
     const uint32_t cs = wave_sum_u32(ns);
@@ -606,7 +705,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
 // n_queues), which under
 // round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
 // the other chunks when its own runs dry.
-template <int S, typename R, int SYNC, bool LAB, bool EX, int K>
+template <int S, typename R, int SYNC, bool LAB, bool EX, int K, bool VEC = false>
 __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
                                                const RayView *__restrict__ views,
                                                const Tile *__restrict__ tiles) {
@@ -644,9 +743,14 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
                        (lane >> tw_log2);
         uint32_t ns = 0;
         const bool in_image = pi < v.width && pj < v.height;
-        const double val = pixel_value<S, R, SYNC, LAB, EX, K>(v, pi, pj, in_image,
-                                                            use_tab ? wave_tab : nullptr, ns);
-        if (in_image) store_pixel(v, pi, pj, val);
+        double ext[3];
+        const double val = pixel_value<S, R, SYNC, LAB, EX, K, VEC>(
+            v, pi, pj, in_image, use_tab ? wave_tab : nullptr, ns, ext);
+        if (in_image) {
+            store_pixel(v, pi, pj, val);
+            if constexpr (VEC)
+                for (int c = 1; c < v.n_chan; c++) store_pixel(v, pi, pj, ext[c - 1], c);
+        }
         const double fs = wave_sum(val);
         const uint32_t cs = wave_sum_u32(ns);
         if (lane == 0) {
@@ -673,6 +777,19 @@ __global__ void __launch_bounds__(256) k_popcount(const uint32_t *bm, uint64_t w
         c += __popc(bm[i]);
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
     if ((threadIdx.x & 63) == 0) atomicAdd(out, c);
+}
+
+// Emissivity fields of n records (the first field of each) into a packed
+// array of the same indexing.
+template <int S>
+__global__ void __launch_bounds__(256) k_pack_j(const typename RecT<S>::raw *__restrict__ rec,
+                                                typename JFieldT<S>::raw *__restrict__ out,
+                                                uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if constexpr (S == ST_F64 || S == ST_F32) out[i] = rec[i].x;
+        else out[i] = (unsigned short)(rec[i].x & 0xffffu);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long *p, uint64_t n,
@@ -786,7 +903,8 @@ static hipError_t plain_impl(const RayView &v, double *flux_acc, unsigned long l
                              hipStream_t s) {
     const dim3 g((unsigned)(((uint64_t)v.width * v.height + 255) / 256)), b(256);
     const bool lab = v.n_blocks > 0, ex = (v.flags & F_EXACT) != 0;
-    if (lab && ex) hipLaunchKernelGGL((k_plain<S, R, true, true>), g, b, 0, s, v, flux_acc, step_acc);
+    if (v.n_chan > 1) hipLaunchKernelGGL((k_plain<S, R, false, false, true>), g, b, 0, s, v, flux_acc, step_acc);
+    else if (lab && ex) hipLaunchKernelGGL((k_plain<S, R, true, true>), g, b, 0, s, v, flux_acc, step_acc);
     else if (lab) hipLaunchKernelGGL((k_plain<S, R, true, false>), g, b, 0, s, v, flux_acc, step_acc);
     else if (ex) hipLaunchKernelGGL((k_plain<S, R, false, true>), g, b, 0, s, v, flux_acc, step_acc);
     else hipLaunchKernelGGL((k_plain<S, R, false, false>), g, b, 0, s, v, flux_acc, step_acc);
@@ -820,6 +938,18 @@ static void batch_launch_k(const BatchLaunch &bl, bool k8, int grid_blocks, hipS
 template <int S, typename R>
 static hipError_t batch_impl(const BatchLaunch &bl, int variant, int grid_blocks, hipStream_t s) {
     const bool k8 = (variant & KV_K8) != 0;
+    if (variant & KV_VEC) {
+        // vector stacks: own marching mode only (no depth sync, labels or
+        // exact time)
+        const dim3 g((unsigned)grid_blocks), b(256);
+        if (k8)
+            hipLaunchKernelGGL((k_batch<S, R, 0, false, false, 8, true>), g, b, 0, s, bl, bl.views,
+                               bl.tiles);
+        else
+            hipLaunchKernelGGL((k_batch<S, R, 0, false, false, 4, true>), g, b, 0, s, bl, bl.views,
+                               bl.tiles);
+        return hipGetLastError();
+    }
     switch (variant & 7) {
         case 0: batch_launch_k<S, R, 0, false, false>(bl, k8, grid_blocks, s); break;
         case 1: batch_launch_k<S, R, 1, false, false>(bl, k8, grid_blocks, s); break;
@@ -935,6 +1065,28 @@ hipError_t launch_rebrick(int store, const StackDev &from, const StackDev &to, v
         case ST_BF16: return rebrick_impl<8>(from, to, dst, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack_j(int store, const void *records, void *out, uint64_t n, hipStream_t s) {
+    const dim3 g(grid_for(n, 1u << 15)), b(256);
+    switch (store) {
+        case ST_F64:
+            hipLaunchKernelGGL(k_pack_j<ST_F64>, g, b, 0, s, (const rec_f64 *)records, (double *)out, n);
+            break;
+        case ST_F32:
+            hipLaunchKernelGGL(k_pack_j<ST_F32>, g, b, 0, s, (const rec_f32 *)records, (float *)out, n);
+            break;
+        case ST_F16:
+            hipLaunchKernelGGL(k_pack_j<ST_F16>, g, b, 0, s, (const rec_h16 *)records,
+                               (unsigned short *)out, n);
+            break;
+        case ST_BF16:
+            hipLaunchKernelGGL(k_pack_j<ST_BF16>, g, b, 0, s, (const rec_h16 *)records,
+                               (unsigned short *)out, n);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,

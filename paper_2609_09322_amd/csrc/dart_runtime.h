@@ -40,6 +40,13 @@ struct dart_stack {
     dart::Block *dev_blocks = nullptr;
     std::atomic<int> refs{0};
     bool labelled() const { return !parts.empty(); }
+    // vector stack: its components (owned by the caller, counted in refs);
+    // dev is component 0's
+    std::vector<dart_stack *> comps;
+    void *packed = nullptr;             // emissivity of components 1.., packed (device)
+    std::vector<uint64_t> packed_gen;   // the components' generations when packed
+    bool vector() const { return !comps.empty(); }
+    int channels() const { return comps.empty() ? 1 : (int)comps.size(); }
 };
 
 namespace dart {
@@ -52,12 +59,17 @@ dart_status resolve_view(const dart_stack *s, const dart_view *v, RayView *rv);
 void note_use(const dart_stack *s, hipStream_t stream);
 bool stack_busy(const dart_stack *s);
 dart_tuning tuning_for(const dart_stack *s);
+// Vector stacks: repacks the components' emissivity on `stream` if any
+// component was refilled since it was packed (after renders that read the
+// packed copy have finished).  No-op for other stacks.
+dart_status refresh_vector(const dart_stack *s, hipStream_t stream);
 
 // One launch group of a batch: views of one storage type and ray precision.
 struct Group {
     int store = 0;
     bool f64 = false;
     bool labelled = false;  // views of labelled stacks (kernels with the block loop)
+    bool vec = false;       // views of vector stacks
     bool exact = false;     // views with exact temporal integration
     std::vector<RayView> views;
     std::vector<Tile> tiles;

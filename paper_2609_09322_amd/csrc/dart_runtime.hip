@@ -191,6 +191,7 @@ static dart_status set_epochs_impl(dart_stack *s, int32_t m0, int32_t count, dar
                                    hipStream_t stream) {
     if (!s) return fail(DART_E_INVAL, "stack is NULL");
     if (s->labelled()) return fail(DART_E_INVAL, "fill the sub-domains of a labelled stack instead");
+    if (s->vector()) return fail(DART_E_INVAL, "fill the components of a vector stack instead");
     if (!j || !beta) return fail(DART_E_INVAL, "emissivity/velocity is NULL");
     if (m0 < 0 || count < 1 || m0 + count > s->dev.n_epochs)
         return fail(DART_E_INVAL, "epoch range [%d, %d) outside [0, %d)", m0, m0 + count,
@@ -309,12 +310,16 @@ extern "C" dart_status dart_free_epochs(dart_stack *s) {
     if (!s) return fail(DART_E_INVAL, "stack is NULL");
     if (stack_busy(s)) return fail(DART_E_BUSY, "renders that read this stack are in flight");
     if (s->refs.load() > 0)
-        return fail(DART_E_BUSY, "the stack is a sub-domain of %d labelled stack(s)", s->refs.load());
+        return fail(DART_E_BUSY, "the stack is held by %d labelled or vector stack(s)",
+                    s->refs.load());
     for (auto &u : s->uses) (void)hipEventDestroy(u.second);
     if (s->labelled()) {
         // the grids belong to the sub-domains
         (void)hipFree(s->dev_blocks);
         for (dart_stack *p : s->parts) p->refs--;
+    } else if (s->vector()) {
+        (void)hipFree(s->packed);
+        for (dart_stack *c : s->comps) c->refs--;
     } else {
         (void)hipFree((void *)s->dev.data);
         (void)hipFree((void *)s->dev.times);
@@ -332,7 +337,8 @@ extern "C" dart_status dart_labelled_create(dart_stack *const *blocks, int32_t n
     for (int32_t i = 0; i < n_blocks; i++) {
         const dart_stack *b = blocks[i];
         if (!b) return fail(DART_E_INVAL, "blocks[%d] is NULL", i);
-        if (b->labelled()) return fail(DART_E_INVAL, "blocks[%d] is itself a labelled stack", i);
+        if (b->labelled() || b->vector())
+            return fail(DART_E_INVAL, "blocks[%d] is itself a labelled or vector stack", i);
         for (int32_t k = 0; k < i; k++)
             if (blocks[k] == b) return fail(DART_E_INVAL, "blocks[%d] repeats blocks[%d]", i, k);
         if (b->storage != b0->storage) return fail(DART_E_INVAL, "blocks[%d]: another storage type", i);
@@ -377,6 +383,84 @@ extern "C" dart_status dart_labelled_create(dart_stack *const *blocks, int32_t n
     return DART_OK;
 }
 
+// Bytes of one packed emissivity value, and of one component's packed array.
+static uint64_t packed_bytes(const dart_stack *s) {
+    return (uint64_t)s->dev.epoch_stride * s->dev.n_epochs * (record_bytes(s->dev.store) / 4);
+}
+
+static hipError_t pack_components(dart_stack *s, hipStream_t stream) {
+    const uint64_t n = (uint64_t)s->dev.epoch_stride * s->dev.n_epochs;
+    for (size_t c = 1; c < s->comps.size(); c++) {
+        hipError_t e = launch_pack_j(s->dev.store, s->comps[c]->dev.data,
+                                     (char *)s->packed + (c - 1) * packed_bytes(s), n, stream);
+        if (e != hipSuccess) return e;
+    }
+    s->packed_gen.clear();
+    for (dart_stack *c : s->comps) s->packed_gen.push_back(c->generation);
+    return hipSuccess;
+}
+
+extern "C" dart_status dart_vector_create(dart_stack *const *components, int32_t n,
+                                          dart_stack **out) {
+    if (out) *out = nullptr;
+    if (!components || !out) return fail(DART_E_INVAL, "bad vector-stack arguments");
+    if (n < 2 || n > 4) return fail(DART_E_INVAL, "a vector stack has 2 to 4 components, not %d", n);
+    const dart_stack *c0 = components[0];
+    for (int32_t i = 0; i < n; i++) {
+        const dart_stack *c = components[i];
+        if (!c) return fail(DART_E_INVAL, "components[%d] is NULL", i);
+        if (c->labelled() || c->vector())
+            return fail(DART_E_INVAL, "components[%d] is a labelled or vector stack", i);
+        for (int32_t k = 0; k < i; k++)
+            if (components[k] == c) return fail(DART_E_INVAL, "components[%d] repeats components[%d]", i, k);
+        if (c->storage != c0->storage) return fail(DART_E_INVAL, "components[%d]: another storage type", i);
+        if (c->device != c0->device) return fail(DART_E_INVAL, "components[%d]: another device", i);
+        if (c->times != c0->times) return fail(DART_E_INVAL, "components[%d]: other epoch times", i);
+        for (int a = 0; a < 3; a++)
+            if (c->dev.n[a] != c0->dev.n[a] || c->dev.cell[a] != c0->dev.cell[a] ||
+                c->dev.lb[a] != c0->dev.lb[a])
+                return fail(DART_E_INVAL, "components[%d]: another grid or brick shape", i);
+        if (c->dev.epoch_stride != c0->dev.epoch_stride)
+            return fail(DART_E_INVAL, "components[%d]: another layout", i);
+        if (c->placed != c0->placed)
+            return fail(DART_E_INVAL, "components[%d]: another placement", i);
+        for (int a = 0; a < 3; a++)
+            if (c->placed && (c->origin[a] != c0->origin[a] || c->centre[a] != c0->centre[a]))
+                return fail(DART_E_INVAL, "components[%d]: another placement", i);
+        for (size_t m = 0; m < c->filled.size(); m++)
+            if (!c->filled[m]) return fail(DART_E_INVAL, "components[%d]: epoch %zu never filled", i, m);
+    }
+    dart_stack *s = new dart_stack;
+    s->dev = c0->dev;
+    s->storage = c0->storage;
+    s->times = c0->times;
+    s->filled.assign(c0->filled.size(), 1);
+    s->device = c0->device;
+    s->placed = c0->placed;
+    for (int a = 0; a < 3; a++) {
+        s->origin[a] = c0->origin[a];
+        s->centre[a] = c0->centre[a];
+    }
+    for (int32_t i = 0; i < n; i++) s->comps.push_back(components[i]);
+    // the other components' emissivity, packed one value per record index
+    HIP_TRY(hipSetDevice(c0->device), "hipSetDevice");
+    hipError_t e = hipMalloc(&s->packed, (n - 1) * packed_bytes(s));
+    if (e == hipSuccess) e = pack_components(s, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        (void)hipFree(s->packed);
+        delete s;
+        return hip_fail(e, "pack vector components");
+    }
+    s->bytes = (n - 1) * packed_bytes(s);
+    for (int32_t i = 0; i < n; i++) {
+        s->bytes += components[i]->bytes;
+        components[i]->refs++;
+    }
+    *out = s;
+    return DART_OK;
+}
+
 extern "C" dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info *info) {
     if (!s || !info) return fail(DART_E_INVAL, "NULL argument");
     for (int a = 0; a < 3; a++) {
@@ -399,7 +483,8 @@ extern "C" dart_status dart_stack_set_placement(dart_stack *s, const double orig
                                                 const double centre[3]) {
     if (!s || !origin || !centre) return fail(DART_E_INVAL, "NULL argument");
     if (s->labelled()) return fail(DART_E_INVAL, "a labelled stack is placed by its sub-domains");
-    if (s->refs.load() > 0) return fail(DART_E_BUSY, "the stack is a sub-domain of a labelled stack");
+    if (s->vector()) return fail(DART_E_INVAL, "a vector stack is placed by its components");
+    if (s->refs.load() > 0) return fail(DART_E_BUSY, "the stack is held by a labelled or vector stack");
     for (int a = 0; a < 3; a++)
         if (!isfinite(origin[a]) || !isfinite(centre[a]))
             return fail(DART_E_INVAL, "origin and centre must be finite");
@@ -423,7 +508,8 @@ extern "C" dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3],
     }
     if (cells > 4096) return fail(DART_E_INVAL, "brick larger than 4096 cells");
     if (s->labelled()) return fail(DART_E_INVAL, "re-lay the sub-domains of a labelled stack before joining them");
-    if (s->refs.load() > 0) return fail(DART_E_BUSY, "the stack is a sub-domain of a labelled stack");
+    if (s->vector()) return fail(DART_E_INVAL, "re-lay the components of a vector stack before joining them");
+    if (s->refs.load() > 0) return fail(DART_E_BUSY, "the stack is held by a labelled or vector stack");
     if (stack_busy(s)) return fail(DART_E_BUSY, "renders that read this stack are in flight");
     if (lb[0] == s->dev.lb[0] && lb[1] == s->dev.lb[1] && lb[2] == s->dev.lb[2]) return DART_OK;
     hipStream_t stream = (hipStream_t)hip_stream;
@@ -520,6 +606,8 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
                                   "it does not combine with DART_NEAREST_EPOCH");
     if ((v->flags & DART_ACCUMULATE) && !(v->flags & DART_DEVICE_PTRS))
         return fail(DART_E_INVAL, "DART_ACCUMULATE needs a device image (DART_DEVICE_PTRS)");
+    if (s->vector() && (v->flags & DART_EXACT_TIME))
+        return fail(DART_E_INVAL, "DART_EXACT_TIME is not available for vector stacks");
     memset(rv, 0, sizeof(*rv));
     const dart_stack *geo = s->labelled() ? s->parts[0] : s;  // camera centre, tile costs
     double st, ct, sp, cp;
@@ -562,6 +650,9 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     rv->st = s->dev;
     rv->blocks = s->dev_blocks;
     rv->n_blocks = (int32_t)s->parts.size();
+    rv->n_chan = s->channels();
+    for (int c = 1; c < rv->n_chan; c++)
+        rv->chan_data[c - 1] = (const char *)s->packed + (c - 1) * packed_bytes(s);
     const std::vector<double> &t = s->times;
     const int M = (int)t.size();
     if (v->flags & DART_NO_LOOKBACK) {
@@ -671,10 +762,12 @@ extern "C" dart_status dart_render(const dart_stack *s, const dart_view *v, void
     dart_status st = resolve_view(s, v, &rv);
     if (st != DART_OK) return st;
     hipStream_t stream = (hipStream_t)hip_stream;
+    st = refresh_vector(s, stream);
+    if (st != DART_OK) return st;
     Workspace *ws = get_workspace(stream);
     std::lock_guard<std::mutex> g(ws->mu);
     const bool dev_img = (v->flags & DART_DEVICE_PTRS) != 0;
-    const size_t img_bytes = (size_t)v->width * v->height * (rv.out_f64 ? 8 : 4);
+    const size_t img_bytes = (size_t)rv.n_chan * v->width * v->height * (rv.out_f64 ? 8 : 4);
     HIP_TRY(ws_reserve(ws, 1, 0, dev_img ? 0 : img_bytes / 8 + 1, 0), "workspace");
     rv.image = dev_img ? image : (void *)ws->img;
     rv.acc_index = 0;
@@ -732,6 +825,22 @@ extern "C" dart_status dart_get_tuning(dart_tuning *t) {
     if (!t) return fail(DART_E_INVAL, "tuning is NULL");
     std::lock_guard<std::mutex> g(g_tune_mu);
     *t = g_tuning;
+    return DART_OK;
+}
+
+dart_status dart::refresh_vector(const dart_stack *cs, hipStream_t stream) {
+    if (!cs || !cs->vector()) return DART_OK;
+    dart_stack *s = const_cast<dart_stack *>(cs);
+    bool stale = false;
+    for (size_t c = 0; c < s->comps.size(); c++)
+        stale = stale || s->comps[c]->generation != s->packed_gen[c];
+    if (!stale) return DART_OK;
+    {
+        // renders still reading the packed copy must finish first
+        std::lock_guard<std::mutex> g(s->mu);
+        for (auto &u : s->uses) HIP_TRY(hipEventSynchronize(u.second), "wait for renders");
+    }
+    HIP_TRY(pack_components(s, stream), "pack vector components");
     return DART_OK;
 }
 
@@ -794,7 +903,7 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         if (!images[i]) return fail(DART_E_INVAL, "images[%d] is NULL", i);
         rv.image = images[i];
         rv.acc_index = i;
-        const int key = rv.st.store * 8 + ((rv.flags & F_F64_DDA) ? 4 : 0) +
+        const int key = rv.st.store * 16 + (rv.n_chan > 1 ? 8 : 0) + ((rv.flags & F_F64_DDA) ? 4 : 0) +
                         (rv.n_blocks > 0 ? 2 : 0) + ((rv.flags & F_EXACT) ? 1 : 0);
         auto it = gindex.find(key);
         if (it == gindex.end()) {
@@ -804,6 +913,7 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             groups.back().f64 = (rv.flags & F_F64_DDA) != 0;
             groups.back().labelled = rv.n_blocks > 0;
             groups.back().exact = (rv.flags & F_EXACT) != 0;
+            groups.back().vec = rv.n_chan > 1;
         }
         Group &g = groups[it->second];
         const uint32_t vi = (uint32_t)g.views.size();
@@ -956,8 +1066,10 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
         for (uint32_t q = 0; q <= g.n_queues; q++) bl.q_begin[q] = g.q_begin[q];
         bl.flux_acc = (double *)acc;
         bl.step_acc = acc + n;
-        const int variant = (tun.depth_sync > 0 ? KV_SYNC : 0) | (g.labelled ? KV_LABELLED : 0) |
-                            (g.exact ? KV_EXACT : 0) | (tun.cells_per_batch == 8 ? KV_K8 : 0);
+        const int variant = g.vec ? (KV_VEC | (tun.cells_per_batch == 8 ? KV_K8 : 0))
+                                  : (tun.depth_sync > 0 ? KV_SYNC : 0) |
+                                        (g.labelled ? KV_LABELLED : 0) | (g.exact ? KV_EXACT : 0) |
+                                        (tun.cells_per_batch == 8 ? KV_K8 : 0);
         e = launch_batch(g.store, g.f64, variant, bl, blocks, stream);
         if (e != hipSuccess) return e;
     }
@@ -1018,6 +1130,10 @@ extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const 
         }
         return DART_OK;
     }
+    for (int32_t i = 0; i < n; i++) {
+        dart_status st = refresh_vector(stacks[i], stream);
+        if (st != DART_OK) return st;
+    }
     const dart_tuning tun = tuning_for(stacks[0]);
     Workspace *ws = get_workspace(stream);
     std::lock_guard<std::mutex> g(ws->mu);
@@ -1044,7 +1160,7 @@ extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const 
     for (int32_t i = 0; i < n; i++) {
         if (!(views[i].flags & DART_DEVICE_PTRS)) {
             img_off[i] = img_bytes;
-            const size_t b = (size_t)views[i].width * views[i].height *
+            const size_t b = (size_t)stacks[i]->channels() * views[i].width * views[i].height *
                              (views[i].out_dtype == DART_F64 ? 8 : 4);
             img_bytes += (b + 255) & ~(size_t)255;
         }
@@ -1112,7 +1228,7 @@ extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const 
     for (int32_t i = 0; i < n; i++) {
         if (!(views[i].flags & DART_DEVICE_PTRS)) {
             any_host = true;
-            const size_t b = (size_t)views[i].width * views[i].height *
+            const size_t b = (size_t)stacks[i]->channels() * views[i].width * views[i].height *
                              (views[i].out_dtype == DART_F64 ? 8 : 4);
             HIP_TRY(hipMemcpyAsync(images[i], (char *)ws->img + img_off[i], b,
                                    hipMemcpyDeviceToHost, stream),
@@ -1140,7 +1256,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
                                      void *hip_stream) {
     if (n < 1 || !stacks || !views) return fail(DART_E_INVAL, "bad autotune arguments");
     for (int32_t i = 0; i < n; i++)
-        if (!stacks[i] || (rebrick && stacks[i]->labelled()))
+        if (!stacks[i] || (rebrick && (stacks[i]->labelled() || stacks[i]->vector())))
             return fail(DART_E_INVAL, "stacks[%d]: NULL, or labelled with rebrick != 0", i);
     hipStream_t stream = (hipStream_t)hip_stream;
     // scratch device images
@@ -1151,7 +1267,8 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         vv[i].flags |= DART_DEVICE_PTRS;
         vv[i].flags &= ~(DART_KERNEL_PLAIN | DART_ACCUMULATE);
         off[i] = total;
-        total += ((size_t)views[i].width * views[i].height * (views[i].out_dtype == DART_F64 ? 8 : 4) + 255) & ~(size_t)255;
+        total += ((size_t)stacks[i]->channels() * views[i].width * views[i].height *
+                      (views[i].out_dtype == DART_F64 ? 8 : 4) + 255) & ~(size_t)255;
     }
     void *buf = nullptr;
     HIP_TRY(hipMalloc(&buf, total), "hipMalloc(autotune images)");

@@ -404,6 +404,7 @@ extern "C" dart_status dart_submit(dart_server *srv, const dart_stack *s, const 
     dart_status st = resolve_view(s, v, &rv);
     if (st != DART_OK) return st;
     if (v->out_dtype != DART_F32) return fail(DART_E_INVAL, "the server renders float32 images");
+    if (s->vector()) return fail(DART_E_INVAL, "the server does not render vector stacks");
     if (v->flags & DART_ACCUMULATE)
         return fail(DART_E_INVAL, "the server does not accept DART_ACCUMULATE");
     std::unique_ptr<Req> r(new Req());

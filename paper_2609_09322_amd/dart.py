@@ -32,7 +32,8 @@ DART_EXACT_TIME = 0x100
 
 EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "dart_free_epochs",
            "dart_stack_get_info", "dart_stack_rebrick", "dart_stack_set_placement",
-           "dart_labelled_create", "dart_streamer_create", "dart_streamer_render",
+           "dart_labelled_create", "dart_vector_create", "dart_streamer_create",
+           "dart_streamer_render",
            "dart_streamer_get_stats", "dart_streamer_destroy", "dart_render", "dart_render_batch",
            "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples", "dart_count_lines",
            "dart_record_bytes", "dart_bandwidth_probe", "dart_server_create", "dart_submit",
@@ -113,6 +114,7 @@ def _load():
         "dart_stack_rebrick": [_P, _P, _P],
         "dart_stack_set_placement": [_P, _P, _P],
         "dart_labelled_create": [_P, I32, _P],
+        "dart_vector_create": [_P, I32, _P],
         "dart_streamer_create": [_P, _P, I32, _P, ctypes.c_int, I32, _P, _P],
         "dart_streamer_render": [_P, ctypes.c_int, _P, _P, U32, _P, I32, _P, _P, _P, _P],
         "dart_streamer_get_stats": [_P, _P],
@@ -274,6 +276,17 @@ def dart_labelled_create(blocks) -> Stack:
     _check(_load().dart_labelled_create(arr, len(blocks), ctypes.byref(out)))
     s = Stack(out.value)
     s.parts = list(blocks)
+    return s
+
+
+def dart_vector_create(components) -> Stack:
+    """A vector stack over 2-4 component stacks (which it keeps alive); its
+    renders fill images of shape [n_components, height, width]."""
+    arr = (ctypes.c_void_p * len(components))(*[c.handle for c in components])
+    out = ctypes.c_void_p()
+    _check(_load().dart_vector_create(arr, len(components), ctypes.byref(out)))
+    s = Stack(out.value)
+    s.parts = list(components)
     return s
 
 
