@@ -831,15 +831,14 @@ extern "C" dart_status dart_get_tuning(dart_tuning *t) {
 dart_status dart::refresh_vector(const dart_stack *cs, hipStream_t stream) {
     if (!cs || !cs->vector()) return DART_OK;
     dart_stack *s = const_cast<dart_stack *>(cs);
+    // one check-and-repack at a time per vector stack
+    std::lock_guard<std::mutex> g(s->mu);
     bool stale = false;
     for (size_t c = 0; c < s->comps.size(); c++)
         stale = stale || s->comps[c]->generation != s->packed_gen[c];
     if (!stale) return DART_OK;
-    {
-        // renders still reading the packed copy must finish first
-        std::lock_guard<std::mutex> g(s->mu);
-        for (auto &u : s->uses) HIP_TRY(hipEventSynchronize(u.second), "wait for renders");
-    }
+    // renders still reading the packed copy must finish first
+    for (auto &u : s->uses) HIP_TRY(hipEventSynchronize(u.second), "wait for renders");
     HIP_TRY(pack_components(s, stream), "pack vector components");
     return DART_OK;
 }

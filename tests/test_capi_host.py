@@ -71,6 +71,40 @@ def test_library_loads_and_reports_errors_without_gpu():
                                     None) == d.DART_E_INVAL
     assert lib.dart_streamer_destroy(None) == d.DART_E_INVAL
     assert lib.dart_count_lines(None, None, None, None) == d.DART_E_INVAL
+    # vector stacks: 2 to 4 components
+    out = ctypes.c_void_p(1)
+    assert lib.dart_vector_create(None, 2, ctypes.byref(out)) == d.DART_E_INVAL
+    assert out.value is None
+    comps = (ctypes.c_void_p * 5)()
+    for n in (0, 1, 5):
+        assert lib.dart_vector_create(comps, n, ctypes.byref(out)) == d.DART_E_INVAL
+    assert "2 to 4" in d.dart_last_error()
+
+
+def test_tuning_checks_without_gpu():
+    """dart_set_tuning validates every field on the host; a rejected tuning
+    leaves the current one in place."""
+    import paper_2609_09322_amd as d
+    saved = d.dart_get_tuning()
+    for bad in (dict(cells_per_batch=5), dict(cells_per_batch=16), dict(order=5),
+                dict(order=-1), dict(depth_sync=65)):
+        args = dict(order=3, orient=0, depth_sync=0, cells_per_batch=8)
+        args.update(bad)
+        with pytest.raises(d.DartError) as ei:
+            d.dart_set_tuning(64, 1, 8, **args)
+        assert ei.value.status == d.DART_E_INVAL
+    with pytest.raises(d.DartError):
+        d.dart_set_tuning(48, 1, 8)          # not 64 pixels per tile
+    with pytest.raises(d.DartError):
+        d.dart_set_tuning(64, 1, 6)          # waves per CU not a multiple of 4
+    got = d.dart_get_tuning()
+    assert (got.tile_w, got.tile_h, got.waves_per_cu, got.order, got.cells_per_batch) == \
+        (saved.tile_w, saved.tile_h, saved.waves_per_cu, saved.order, saved.cells_per_batch)
+    for k in (0, 4, 8):
+        d.dart_set_tuning(64, 1, 8, 4, 0, 2, k)
+        assert d.dart_get_tuning().cells_per_batch == k
+    d.dart_set_tuning(saved.tile_w, saved.tile_h, saved.waves_per_cu, saved.order,
+                      saved.orient, saved.depth_sync, saved.cells_per_batch)
 
 
 def test_structs_match_header_layout():
