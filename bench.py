@@ -188,6 +188,24 @@ def bandwidth_probe(dart, torch, stream, nbytes=4 << 30, reps=10):
     return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
 
 
+def read_probe(dart, torch, stream, nbytes=4 << 30, reps=10):
+    """GB/s of a read-only pass over nbytes (dart_bandwidth_probe without a
+    destination): the reference for a kernel that mostly reads."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dart.dart_bandwidth_probe(None, src, nbytes, 2, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        dart.dart_bandwidth_probe(None, src, nbytes, reps, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    del src
+    torch.cuda.empty_cache()
+    return nbytes * reps / (ms * 1e-3) / 1e9
+
+
 def oracle_sample(host, times, views, n_rays, seed, threads, kind="f32"):
     """Runs the FP64 oracle on n_rays random pixels spread over the views.
     Returns (per-view list of (pixels, values), total cell-steps, seconds)."""
@@ -342,6 +360,7 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
     # in profile mode a 1 GiB copy (2 launches) runs as the counter calibration kernel
     bw = bandwidth_probe(dart, torch, stream, nbytes=(1 << 30) if args.profile else (4 << 30),
                          reps=2 if args.profile else 10)
+    rd = None if args.profile else read_probe(dart, torch, stream)
     achieved = compulsory / (kernel_ms * 1e-3) / 1e9 if compulsory else None
     roof = None
     if achieved is not None:
@@ -355,6 +374,9 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
                                     "bytes + image bytes",
                 "measured_copy_gbs": bw,
                 "frac_of_measured_copy": (achieved / bw) if bw else None,
+                "measured_read_gbs": rd,
+                "fetched_over_measured_read": (traffic / (kernel_ms * 1e-3) / 1e9 / rd)
+                if (traffic and rd) else None,
                 "gather_bytes_gbs": cell_steps * 2 * rec_bytes / (kernel_ms * 1e-3) / 1e9,
                 "line_bytes_per_launch": line_bytes,
                 "line_bytes_definition": "distinct 128-B lines of the resident layout holding "

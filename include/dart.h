@@ -335,7 +335,9 @@ dart_status dart_count_lines(const dart_stack *s, const dart_view *v, uint64_t *
 dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_out);
 
 /* Streaming copy of `bytes` (multiple of 16) from src to dst, both device
- * memory: the measured HBM bandwidth reference. reps > 0 copies are enqueued. */
+ * memory: the measured HBM bandwidth reference. reps > 0 copies are enqueued.
+ * dst = NULL: a read-only pass over src instead (each 16-byte word loaded
+ * once, nothing written): the reference for kernels that mostly read. */
 dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t bytes, int32_t reps,
                                  void *hip_stream);
 

@@ -1485,11 +1485,46 @@ extern "C" dart_status dart_count_lines(const dart_stack *s, const dart_view *v,
     return count_marked(s, v, line_log2, lines_out, hip_stream);
 }
 
+// Read-only bandwidth probe: every 16-byte word of src is loaded once and
+// folded into a per-thread checksum, which is stored only if it equals one
+// particular value.  The store keeps the loads from being removed; for the
+// bench's buffer of ones it never happens (and if it did, the sink is valid
+// device memory).
+__global__ void __launch_bounds__(256) k_read_probe(const uint4 *__restrict__ src, uint64_t n,
+                                                    uint32_t *__restrict__ sink) {
+    uint32_t acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4 w = src[i];
+        acc ^= w.x ^ w.y ^ w.z ^ w.w;
+    }
+    if (acc == 0x7fc00001u) sink[0] = acc;
+}
+
 extern "C" dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t bytes,
                                             int32_t reps, void *hip_stream) {
-    if (!dst || !src || bytes == 0 || bytes % 16 || reps < 1)
+    if (!src || bytes == 0 || bytes % 16 || reps < 1)
         return fail(DART_E_INVAL, "bad probe arguments");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (!dst) {
+        // read-only: the sink is never written for finite inputs, but it must
+        // be valid device memory
+        static uint32_t *sink = nullptr;
+        static std::mutex sink_mu;
+        {
+            std::lock_guard<std::mutex> g(sink_mu);
+            if (!sink) HIP_TRY(hipMalloc((void **)&sink, 256), "hipMalloc(probe sink)");
+        }
+        const uint64_t n = bytes / 16;
+        const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 1u << 14);
+        for (int32_t r = 0; r < reps; r++) {
+            hipLaunchKernelGGL(k_read_probe, dim3((unsigned)blocks), dim3(256), 0, stream,
+                               (const uint4 *)src, n, sink);
+            HIP_TRY(hipGetLastError(), "read probe kernel");
+        }
+        return DART_OK;
+    }
     for (int32_t r = 0; r < reps; r++)
-        HIP_TRY(launch_copy(dst, src, bytes, (hipStream_t)hip_stream), "copy kernel");
+        HIP_TRY(launch_copy(dst, src, bytes, stream), "copy kernel");
     return DART_OK;
 }
