@@ -375,6 +375,7 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
                 "measured_copy_gbs": bw,
                 "frac_of_measured_copy": (achieved / bw) if bw else None,
                 "measured_read_gbs": rd,
+                "frac_of_measured_read": (achieved / rd) if rd else None,
                 "fetched_over_measured_read": (traffic / (kernel_ms * 1e-3) / 1e9 / rd)
                 if (traffic and rd) else None,
                 "gather_bytes_gbs": cell_steps * 2 * rec_bytes / (kernel_ms * 1e-3) / 1e9,
