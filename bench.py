@@ -152,6 +152,14 @@ def make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage, kin
     return st, times, host
 
 
+def workload_key(args):
+    """Row key of the counter table: the workload, its storage type for the
+    batch, and the options that change the launch."""
+    return ((args.workload if args.workload != "batch" else f"batch-{args.storage}")
+            + ("-exact" if args.exact_time else "")
+            + (f"-sides{args.sides}" if getattr(args, "sides", None) else ""))
+
+
 def time_steps(torch, stream, fn, steps, warmup):
     for _ in range(warmup):
         fn()
@@ -238,7 +246,7 @@ def pix_err(got, ref, img_max):
 def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_spec, gamma,
                         knots, seed, rec_bytes, dtype_name, check_views=None, tune_views=None):
     stream = torch.cuda.Stream()
-    wkey = (args.workload if args.workload != "batch" else f"batch-{args.storage}") + ("-exact" if args.exact_time else "")
+    wkey = workload_key(args)
     keep_host = not args.no_cpu_baseline or args.check
     st, times, host = make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage,
                                      dtype_name, keep_host)
@@ -1096,6 +1104,9 @@ def main():
                          "and compare their sum with the whole (0: skip)")
     ap.add_argument("--storage", default="f16", choices=["f16", "bf16"],
                     help="batch workload: 16-bit storage type")
+    ap.add_argument("--sides", default=None,
+                    help="batch workload: keep only the views with these image sides "
+                         "(comma-separated), for a per-size breakdown")
     ap.add_argument("--requests", type=int, default=6000)
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--rate", type=float, default=200.0)
@@ -1113,7 +1124,7 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="fixed launch shape instead of autotuning: "
                          "tile_w,tile_h,waves_per_cu,order,orient,brick_x,brick_y,brick_z"
-                         "[,depth_sync]")
+                         "[,depth_sync[,cells_per_batch]]")
     ap.add_argument("--profile", action="store_true",
                     help="timed batched loop only (for rocprofv3 runs)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -1121,7 +1132,7 @@ def main():
                          "of a --profile run (with the same --workload/--storage/--tuning)")
     args = ap.parse_args()
     if args.pmc_summary:
-        wkey = (args.workload if args.workload != "batch" else f"batch-{args.storage}") + ("-exact" if args.exact_time else "")
+        wkey = workload_key(args)
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], wkey, normalise_tuning(args.tuning))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -1144,10 +1155,16 @@ def main():
     elif args.workload == "batch":
         import synth
         views = [(th, ph, P, 0.6) for th, ph, P in synth.isotropic_views(64, 1003)]
+        name = (f"uneven batch 384^3, 32 epochs, {args.storage.upper()}, 64 isotropic views, "
+                "sides in {128,256,512,1024}")
+        if args.sides:
+            # one size class of the same 64 views (a breakdown, not the workload)
+            keep = {int(x) for x in args.sides.split(",")}
+            views = [v for v in views if v[2] in keep]
+            name += f", only the {len(views)} views of side {args.sides}"
         storage = dart.DART_F16 if args.storage == "f16" else dart.DART_BF16
         line = run_render_workload(
-            args, dart, torch, f"uneven batch 384^3, 32 epochs, {args.storage.upper()}, 64 isotropic "
-            "views, sides in {128,256,512,1024}", (384, 384, 384), 32, storage, views, 5.0, 4, 3, 8,
+            args, dart, torch, name, (384, 384, 384), 32, storage, views, 5.0, 4, 3, 8,
             args.storage, check_views=8)
     elif args.workload == "serve":
         line = run_serve_workload(args, dart, torch)

@@ -403,11 +403,13 @@ __device__ __forceinline__ R wave_min(R x) {
 // VEC (vector stacks): the same walk, weights and D^p also integrate the
 // emissivity of components 1..n_chan-1, each with its own compensated sum,
 // returned in ext[0..2].
-template <int S, typename R, int SYNC, bool EX, int K, bool VEC = false>
-__device__ __forceinline__ double march(const RayView &v, const StackDev &st,
-                                        const double *centre, int pi, int pj, bool in_image,
-                                        const ldsdouble *tab, uint32_t &nsteps,
-                                        double *ext = nullptr) {
+// SINGLE: one epoch per cell (nearest-epoch mode, or a one-epoch stack), a
+// property of the view and stack, so each lane's walk has no per-cell test.
+template <int S, typename R, int SYNC, bool EX, int K, bool VEC, bool SINGLE>
+__device__ __forceinline__ double march_walk(const RayView &v, const StackDev &st,
+                                             const double *centre, int pi, int pj, bool in_image,
+                                             const ldsdouble *tab, uint32_t &nsteps,
+                                             double *ext) {
     using A = typename std::conditional<S == ST_F64, double, float>::type;
     using V = typename RecT<S>::val;
     using Raw = typename RecT<S>::raw;
@@ -425,7 +427,7 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
     const bool lookback = !(v.flags & F_NO_LOOKBACK);
     const bool beaming = !(v.flags & F_NO_BEAMING);
     const int M = st.n_epochs;
-    const bool single = (v.flags & F_NEAREST) || M == 1;
+    constexpr bool single = SINGLE;
     const bool kahan = !(v.flags & F_NO_KAHAN);
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
     const R gap = (R)v.sync_gap;
@@ -518,7 +520,7 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                         ebase_m = br.m;
                     }
                     GRaw *e0 = ebase;
-                    if (single) {
+                    if constexpr (single) {
                         if (M >= 2) {
                             const bool later =
                                 lookback ? (mid - br.am1) < (br.am - mid) : wt > (R)0.5;
@@ -612,6 +614,19 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
         for (int c = 0; c < NX; c++) ext[c] = (double)xsum[c] - (double)xcomp[c];
     }
     return (double)sum - (double)comp;
+}
+
+template <int S, typename R, int SYNC, bool EX, int K, bool VEC = false>
+__device__ __forceinline__ double march(const RayView &v, const StackDev &st,
+                                        const double *centre, int pi, int pj, bool in_image,
+                                        const ldsdouble *tab, uint32_t &nsteps,
+                                        double *ext = nullptr) {
+    // uniform over the launch's view (flags, epoch count): a scalar branch
+    if ((v.flags & F_NEAREST) || st.n_epochs == 1)
+        return march_walk<S, R, SYNC, EX, K, VEC, true>(v, st, centre, pi, pj, in_image, tab,
+                                                         nsteps, ext);
+    return march_walk<S, R, SYNC, EX, K, VEC, false>(v, st, centre, pi, pj, in_image, tab, nsteps,
+                                                      ext);
 }
 
 // Intensity of pixel (pi, pj): one march through the stack, or, for a labelled
