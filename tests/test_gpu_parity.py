@@ -196,6 +196,56 @@ def _batch_equals_plain_and_oracle(dart, store, torch):
         assert pix_err(got, ref).max() <= TOL[store]
 
 
+@pytest.mark.parametrize("store", ["f32", "f16"])
+@pytest.mark.parametrize("sync", [0, 2])
+def test_one_epoch_walks_mixed_in_a_batch(dart, store, sync):
+    """Views that take one epoch per cell (nearest-epoch mode, a one-epoch
+    stack) and views that interpolate run in one batched launch; each wave
+    picks its walk from its view.  Pixels equal the plain kernel's bit for bit
+    and match the oracle."""
+    import torch
+    dims = (21, 17, 19)
+    j, b, t = synth.random_stack(dims, 5, seed=23, beta_max=0.8)
+    src = np.float32
+    s5 = dart.dart_load_epochs(dims, (1, 1, 1), t, j.astype(src), b.astype(src), _store(dart, store))
+    s1 = dart.dart_load_epochs(dims, (1, 1, 1), t[:1], j[:1].astype(src), b[:1].astype(src),
+                               _store(dart, store))
+    L = synth.diag(dims)
+    tm = float(t.mean())
+    spec = [(s5, 0, 40.0, 30.0, tm), (s5, dart.DART_NEAREST_EPOCH, 40.0, 30.0, tm),
+            (s5, dart.DART_NEAREST_EPOCH | dart.DART_NO_LOOKBACK, 75.0, 200.0, tm),
+            (s1, dart.DART_NO_LOOKBACK, 120.0, 10.0, float(t[0])), (s5, dart.DART_NO_LOOKBACK, 10.0, 80.0, tm),
+            (s1, dart.DART_NEAREST_EPOCH | dart.DART_NO_LOOKBACK, 90.0, 45.0, float(t[0]))]
+    stacks, views = [], []
+    for k, (st, fl, th, ph, to) in enumerate(spec):
+        W, H = 23 + 5 * k, 19 + 3 * k
+        stacks.append(st)
+        views.append(dart.View(th, ph, W, H, 1.1 * L / max(W, H), to, 0.6, fl))
+    saved = dart.dart_get_tuning()
+    dart.dart_set_tuning(16, 4, 8, 3, 1, sync, 8)
+    try:
+        imgs = [torch.zeros((v.height, v.width), dtype=torch.float32, device="cuda") for v in views]
+        flux, steps = dart.dart_render_batch(stacks, views, imgs)
+    finally:
+        dart.dart_set_tuning(saved.tile_w, saved.tile_h, saved.waves_per_cu, saved.order,
+                             saved.orient, saved.depth_sync, saved.cells_per_batch or 4)
+    for k, v in enumerate(views):
+        plain = np.zeros((v.height, v.width), dtype=np.float32)
+        pf, ps_ = dart.dart_render(stacks[k], v, plain)
+        got = imgs[k].cpu().numpy()
+        np.testing.assert_array_equal(got, plain)
+        assert int(steps[k]) == ps_
+        M = 1 if stacks[k] is s1 else 5
+        ost = oracle.Stack(_dequant(j[:M], store).astype(np.float64),
+                           _dequant(b[:M], store).astype(np.float64), t[:M])
+        ref, rs = oracle.render(ost, oracle.View(v.theta_deg, v.phi_deg, v.width, v.height,
+                                                 v.pixel_scale, v.t_obs, v.alpha, v.flags & 7))
+        assert ref.max() > 0, k
+        assert pix_err(got, ref).max() <= TOL[store], (store, sync, k)
+    dart.dart_free_epochs(s1)
+    dart.dart_free_epochs(s5)
+
+
 @pytest.mark.parametrize("on_stream", [False, True])
 def test_replay_follows_a_new_stack(dart, on_stream):
     """A batched call repeated with the same arguments replays its cached plan;
