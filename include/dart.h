@@ -337,7 +337,8 @@ dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_out);
 /* Streaming copy of `bytes` (multiple of 16) from src to dst, both device
  * memory: the measured HBM bandwidth reference. reps > 0 copies are enqueued.
  * dst = NULL: a read-only pass over src instead (each 16-byte word loaded
- * once, nothing written): the reference for kernels that mostly read. */
+ * once, several independent loads in flight per thread, nothing written): the
+ * reference for kernels that mostly read. */
 dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t bytes, int32_t reps,
                                  void *hip_stream);
 

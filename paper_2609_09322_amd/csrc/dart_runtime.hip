@@ -1490,13 +1490,25 @@ extern "C" dart_status dart_count_lines(const dart_stack *s, const dart_view *v,
 // particular value.  The store keeps the loads from being removed; for the
 // bench's buffer of ones it never happens (and if it did, the sink is valid
 // device memory).
+// Each thread keeps READ_PROBE_DEPTH independent 16-B loads in flight per
+// iteration (coalesced across the grid), so the pass measures bandwidth rather
+// than the latency of one load per thread.
+constexpr int READ_PROBE_DEPTH = 8;
+
 __global__ void __launch_bounds__(256) k_read_probe(const uint4 *__restrict__ src, uint64_t n,
                                                     uint32_t *__restrict__ sink) {
     uint32_t acc = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint4 w = src[i];
-        acc ^= w.x ^ w.y ^ w.z ^ w.w;
+         i += stride * READ_PROBE_DEPTH) {
+        uint4 w[READ_PROBE_DEPTH];
+#pragma unroll
+        for (int k = 0; k < READ_PROBE_DEPTH; k++) {
+            const uint64_t ik = i + (uint64_t)k * stride;
+            w[k] = ik < n ? src[ik] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < READ_PROBE_DEPTH; k++) acc ^= w[k].x ^ w[k].y ^ w[k].z ^ w[k].w;
     }
     if (acc == 0x7fc00001u) sink[0] = acc;
 }
