@@ -196,6 +196,24 @@ def bandwidth_probe(dart, torch, stream, nbytes=4 << 30, reps=10):
     return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
 
 
+def gather_probe(dart, torch, stream, nbytes=4 << 30, reps=10):
+    """GB/s of a gather over scattered whole 128-B lines (dart_gather_probe):
+    the reference for a kernel that gathers lines from scattered addresses."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dart.dart_gather_probe(src, nbytes, 2, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        dart.dart_gather_probe(src, nbytes, reps, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    del src
+    torch.cuda.empty_cache()
+    return float(nbytes) * reps / (ms * 1e-3) / 1e9
+
+
 def read_probe(dart, torch, stream, nbytes=4 << 30, reps=10):
     """GB/s of a read-only pass over nbytes (dart_bandwidth_probe without a
     destination): the reference for a kernel that mostly reads."""
@@ -369,6 +387,7 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
     bw = bandwidth_probe(dart, torch, stream, nbytes=(1 << 30) if args.profile else (4 << 30),
                          reps=2 if args.profile else 10)
     rd = None if args.profile else read_probe(dart, torch, stream)
+    gp = None if args.profile else gather_probe(dart, torch, stream)
     achieved = compulsory / (kernel_ms * 1e-3) / 1e9 if compulsory else None
     roof = None
     if achieved is not None:
@@ -386,6 +405,10 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
                 "frac_of_measured_read": (achieved / rd) if rd else None,
                 "fetched_over_measured_read": (traffic / (kernel_ms * 1e-3) / 1e9 / rd)
                 if (traffic and rd) else None,
+                "measured_gather_gbs": gp,
+                "frac_of_measured_gather": (achieved / gp) if gp else None,
+                "fetched_over_measured_gather": (traffic / (kernel_ms * 1e-3) / 1e9 / gp)
+                if (traffic and gp) else None,
                 "gather_bytes_gbs": cell_steps * 2 * rec_bytes / (kernel_ms * 1e-3) / 1e9,
                 "line_bytes_per_launch": line_bytes,
                 "line_bytes_definition": "distinct 128-B lines of the resident layout holding "

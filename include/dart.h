@@ -342,6 +342,15 @@ dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_out);
 dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t bytes, int32_t reps,
                                  void *hip_stream);
 
+/* Gather probe: reads every 128-byte line of src (device memory) once, in a
+ * scattered order (line k is read as line k * odd mod the line count), eight
+ * consecutive threads reading the eight 16-byte words of one line, several
+ * loads in flight per thread.  The bandwidth reference for kernels that gather
+ * whole lines from scattered addresses.  bytes must be 128 times a power of
+ * two (else DART_E_INVAL, nothing enqueued); reps > 0 passes are enqueued on
+ * hip_stream.  Nothing is written. */
+dart_status dart_gather_probe(const void *src, uint64_t bytes, int32_t reps, void *hip_stream);
+
 /* ---------------------------------------------------------------- serving --
  * A render server keeps stacks resident (the caller's) and runs a host
  * scheduler thread that batches requests as they arrive (continuous batching):

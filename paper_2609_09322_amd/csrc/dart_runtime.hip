@@ -1513,6 +1513,65 @@ __global__ void __launch_bounds__(256) k_read_probe(const uint4 *__restrict__ sr
     if (acc == 0x7fc00001u) sink[0] = acc;
 }
 
+// Gather probe: every 128-B line of the buffer read once, in an order that
+// scatters neighbouring lines over the whole buffer (line k goes to line
+// k * odd mod 2^b, a permutation).  Eight consecutive lanes read the eight
+// 16-B words of one line, so a wave's load instruction touches eight unrelated
+// lines: the access pattern of a gather over bricked records, without the
+// reuse.
+__global__ void __launch_bounds__(256) k_gather_probe(const uint4 *__restrict__ src,
+                                                      uint64_t n_lines, uint32_t *__restrict__ sink) {
+    uint32_t acc = 0;
+    const uint64_t nw = n_lines * 8u, mask = n_lines - 1u;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+         i += stride * READ_PROBE_DEPTH) {
+        uint4 w[READ_PROBE_DEPTH];
+#pragma unroll
+        for (int k = 0; k < READ_PROBE_DEPTH; k++) {
+            const uint64_t ik = i + (uint64_t)k * stride;
+            const uint64_t line = ((ik >> 3) * 0x9E3779B97F4A7C15ull) & mask;
+            w[k] = ik < nw ? src[line * 8u + (ik & 7u)] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < READ_PROBE_DEPTH; k++) acc ^= w[k].x ^ w[k].y ^ w[k].z ^ w[k].w;
+    }
+    if (acc == 0x7fc00001u) sink[0] = acc;
+}
+
+// Device word the probes may write (never, for finite inputs); allocated once.
+static hipError_t probe_sink(uint32_t **out) {
+    static uint32_t *sink = nullptr;
+    static std::mutex sink_mu;
+    std::lock_guard<std::mutex> g(sink_mu);
+    if (!sink) {
+        hipError_t e = hipMalloc((void **)&sink, 256);
+        if (e != hipSuccess) {
+            sink = nullptr;
+            return e;
+        }
+    }
+    *out = sink;
+    return hipSuccess;
+}
+
+extern "C" dart_status dart_gather_probe(const void *src, uint64_t bytes, int32_t reps,
+                                         void *hip_stream) {
+    const uint64_t n_lines = bytes / 128u;
+    if (!src || bytes == 0 || bytes % 128u || (n_lines & (n_lines - 1u)) || reps < 1)
+        return fail(DART_E_INVAL, "gather probe: bytes must be 128 times a power of two, reps > 0");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    uint32_t *sink = nullptr;
+    HIP_TRY(probe_sink(&sink), "hipMalloc(probe sink)");
+    const uint64_t blocks = std::min<uint64_t>((n_lines * 8u + 255u) / 256u, 1u << 14);
+    for (int32_t r = 0; r < reps; r++) {
+        hipLaunchKernelGGL(k_gather_probe, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           (const uint4 *)src, n_lines, sink);
+        HIP_TRY(hipGetLastError(), "gather probe kernel");
+    }
+    return DART_OK;
+}
+
 extern "C" dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t bytes,
                                             int32_t reps, void *hip_stream) {
     if (!src || bytes == 0 || bytes % 16 || reps < 1)
@@ -1521,12 +1580,8 @@ extern "C" dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t
     if (!dst) {
         // read-only: the sink is never written for finite inputs, but it must
         // be valid device memory
-        static uint32_t *sink = nullptr;
-        static std::mutex sink_mu;
-        {
-            std::lock_guard<std::mutex> g(sink_mu);
-            if (!sink) HIP_TRY(hipMalloc((void **)&sink, 256), "hipMalloc(probe sink)");
-        }
+        uint32_t *sink = nullptr;
+        HIP_TRY(probe_sink(&sink), "hipMalloc(probe sink)");
         const uint64_t n = bytes / 16;
         const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 1u << 14);
         for (int32_t r = 0; r < reps; r++) {

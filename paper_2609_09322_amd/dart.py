@@ -36,7 +36,7 @@ EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "da
            "dart_streamer_render",
            "dart_streamer_get_stats", "dart_streamer_destroy", "dart_render", "dart_render_batch",
            "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples", "dart_count_lines",
-           "dart_record_bytes", "dart_bandwidth_probe", "dart_server_create", "dart_submit",
+           "dart_record_bytes", "dart_bandwidth_probe", "dart_gather_probe", "dart_server_create", "dart_submit",
            "dart_poll", "dart_wait", "dart_server_destroy", "dart_server_get_stats",
            "dart_last_error", "dart_version"]
 
@@ -128,6 +128,7 @@ def _load():
         "dart_count_lines": [_P, _P, _P, _P],
         "dart_record_bytes": [_P, _P],
         "dart_bandwidth_probe": [_P, _P, U64, I32, _P],
+        "dart_gather_probe": [_P, U64, I32, _P],
         "dart_server_create": [ctypes.c_size_t, I32, I32, _P],
         "dart_submit": [_P, _P, _P, _P, _P],
         "dart_poll": [_P, U64, _P, _P, _P, _P],
@@ -374,6 +375,11 @@ def dart_bandwidth_probe(dst, src, nbytes, reps=1, stream=None):
     dp, _ = _ptr(dst)
     sp, _ = _ptr(src)
     _check(_load().dart_bandwidth_probe(dp, sp, int(nbytes), int(reps), _stream(stream)))
+
+
+def dart_gather_probe(src, nbytes, reps=1, stream=None):
+    sp, _ = _ptr(src)
+    _check(_load().dart_gather_probe(sp, int(nbytes), int(reps), _stream(stream)))
 
 
 class Server:

@@ -71,6 +71,13 @@ def test_library_loads_and_reports_errors_without_gpu():
                                     None) == d.DART_E_INVAL
     assert lib.dart_streamer_destroy(None) == d.DART_E_INVAL
     assert lib.dart_count_lines(None, None, None, None) == d.DART_E_INVAL
+    # probes: sizes checked before any device call
+    assert lib.dart_gather_probe(None, ctypes.c_uint64(1 << 20), 1, None) == d.DART_E_INVAL
+    for nbytes in (0, 100, 128 * 3, 128 * 1000):
+        assert lib.dart_gather_probe(ctypes.c_void_p(16), ctypes.c_uint64(nbytes), 1,
+                                     None) == d.DART_E_INVAL
+    assert "power of two" in d.dart_last_error()
+    assert lib.dart_bandwidth_probe(None, None, ctypes.c_uint64(16), 1, None) == d.DART_E_INVAL
     # vector stacks: 2 to 4 components
     out = ctypes.c_void_p(1)
     assert lib.dart_vector_create(None, 2, ctypes.byref(out)) == d.DART_E_INVAL
