@@ -415,3 +415,24 @@ def test_validation_errors(dart):
     s32 = dart.dart_load_epochs(dims, (1, 1, 1), t, j.astype(np.float32), b.astype(np.float32), dart.DART_F32)
     with pytest.raises(dart.DartError):
         dart.dart_render(s32, dart.View(0, 0, 4, 4, 1.0, 0.5, 0.6, 0, dart.DART_F64), img)
+
+
+def test_bandwidth_probes(dart):
+    """The measurement probes: the copy writes an exact copy, the read-only and
+    gather passes run over a buffer whose size is not a multiple of their grid
+    (and the gather probe rejects a line count that is not a power of two)."""
+    import torch
+    n = (1 << 20) + 16 * 37  # bytes: a ragged tail for the copy and the read pass
+    src = torch.arange(n // 4, dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    dart.dart_bandwidth_probe(dst, src, n, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    dart.dart_bandwidth_probe(None, src, n, 3)
+    g = torch.ones((128 << 12) // 4, dtype=torch.float32, device="cuda")
+    dart.dart_gather_probe(g, 128 << 12, 3)
+    torch.cuda.synchronize()
+    with pytest.raises(dart.DartError) as ei:
+        dart.dart_gather_probe(g, 128 * 3000, 1)
+    assert ei.value.status == dart.DART_E_INVAL
+    assert float(g.sum()) == g.numel()
