@@ -215,26 +215,28 @@ __device__ __forceinline__ bool ray_setup(const RayView &v, const StackDev &st,
 // Step to the neighbour across the nearest face; false when leaving the grid.
 template <typename R>
 __device__ __forceinline__ bool ray_advance(const StackDev &st, Ray<R> &r) {
+    // (the crossing state of a ray that leaves the grid is not used again)
+    bool inside;
     if (r.sa0 <= r.sa1 && r.sa0 <= r.sa2) {
         r.x += r.sx;
-        if ((unsigned)r.x >= (unsigned)st.n[0]) return false;
+        inside = (unsigned)r.x < (unsigned)st.n[0];
         r.c0++;
         r.sb0 = r.sa0;
         r.sa0 = fma((R)r.c0, r.d0, r.b0);
     } else if (r.sa1 <= r.sa2) {
         r.y += r.sy;
-        if ((unsigned)r.y >= (unsigned)st.n[1]) return false;
+        inside = (unsigned)r.y < (unsigned)st.n[1];
         r.c1++;
         r.sb1 = r.sa1;
         r.sa1 = fma((R)r.c1, r.d1, r.b1);
     } else {
         r.z += r.sz;
-        if ((unsigned)r.z >= (unsigned)st.n[2]) return false;
+        inside = (unsigned)r.z < (unsigned)st.n[2];
         r.c2++;
         r.sb2 = r.sa2;
         r.sa2 = fma((R)r.c2, r.d2, r.b2);
     }
-    return true;
+    return inside;
 }
 
 // Epoch bracket in s: a_m = t_obs - t_m decreases with m; the bracket m holds
@@ -376,9 +378,10 @@ constexpr int CELLS_PER_BATCH = 4;
 // caller's reductions); adds the counted cell-steps to nsteps.
 //
 // The walk does not depend on the data it reads, so each lane first walks a
-// batch of cells (chord, epoch weight, record addresses), then requests the
-// 2 x CELLS_PER_BATCH records at once and consumes them after a single wait:
-// many gathers per lane in flight instead of one dependent load per step.
+// batch of K cells (chord, epoch weight, record addresses), then requests the
+// 2K records at once and consumes them after a single wait: many gathers per
+// lane in flight instead of one dependent load per step.  (K is 4 or 8 in the
+// batched kernel, CELLS_PER_BATCH in the plain one.)
 template <typename R>
 __device__ __forceinline__ R wave_min(R x) {
 #pragma unroll
