@@ -1401,15 +1401,19 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         }
     }
     // Stage 3: cells per batch and depth-synchronous marching on the chosen
-    // launch shape.
+    // launch shape.  8 cells per batch are swept first, so that they win ties:
+    // more loads in flight per wave is the better default where the two are
+    // within timing noise, and a stable choice keeps counter rows applicable.
     if (result == DART_OK) {
         std::vector<dart_tuning> c3;
         std::vector<float> c3_ms;
-        c3.push_back(best);
-        c3_ms.push_back((float)best_ms);
-        for (int k : {4, 8})
+        for (int k : {8, 4})
         for (int gap : {0, 1, 2, 3, 4, 6}) {
-            if (k == 4 && gap == 0) continue;  // the launch shape as chosen
+            if (k == 4 && gap == 0) {  // the launch shape as chosen, already timed
+                c3.push_back(best);
+                c3_ms.push_back((float)best_ms);
+                continue;
+            }
             dart_tuning c = best;
             c.cells_per_batch = k;
             c.depth_sync = gap;
