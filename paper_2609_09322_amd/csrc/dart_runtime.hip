@@ -1287,7 +1287,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         for (int w : waves)
             for (int order : orders)
                 for (int orient = 0; orient < 2; orient++)
-                    cands.push_back({sh[0], sh[1], w, order, orient, 0});
+                    cands.push_back({sh[0], sh[1], w, order, orient, 0, 8});
     // Brick candidates: every power-of-two shape holding one 128-B cache line
     // of records.  Which one wins depends on the view set: lines that extend
     // along the rays' directions are used whole by one ray, lines across the
@@ -1353,8 +1353,8 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
     dart_status result = DART_OK;
     // Stage 1: brick shapes under a few representative launch shapes.
     if (rebrick) {
-        const dart_tuning probes[] = {{64, 1, 12, 0, 0, 0}, {64, 1, 12, 0, 1, 0},
-                                      {8, 8, 12, 0, 0, 0}};
+        const dart_tuning probes[] = {{64, 1, 12, 0, 0, 0, 8}, {64, 1, 12, 0, 1, 0, 8},
+                                      {8, 8, 12, 0, 0, 0, 8}};
         std::vector<float> brick_ms;
         for (auto &br : bricks) {
             result = rebrick_all(br);
@@ -1401,15 +1401,16 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         }
     }
     // Stage 3: cells per batch and depth-synchronous marching on the chosen
-    // launch shape.  8 cells per batch are swept first, so that they win ties:
-    // more loads in flight per wave is the better default where the two are
-    // within timing noise, and a stable choice keeps counter rows applicable.
+    // launch shape.  Stages 1 and 2 time 8 cells per batch (more loads in
+    // flight per wave; the better default measured), and 8 is swept first
+    // here, so that it wins ties: a stable choice keeps counter rows
+    // applicable.
     if (result == DART_OK) {
         std::vector<dart_tuning> c3;
         std::vector<float> c3_ms;
         for (int k : {8, 4})
         for (int gap : {0, 1, 2, 3, 4, 6}) {
-            if (k == 4 && gap == 0) {  // the launch shape as chosen, already timed
+            if (k == 8 && gap == 0) {  // the launch shape as chosen, already timed
                 c3.push_back(best);
                 c3_ms.push_back((float)best_ms);
                 continue;
