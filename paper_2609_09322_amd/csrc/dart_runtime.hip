@@ -1544,13 +1544,18 @@ __global__ void __launch_bounds__(256) k_gather_probe(const uint4 *__restrict__ 
     if (acc == 0x7fc00001u) sink[0] = acc;
 }
 
-// Device word the probes may write (never, for finite inputs); allocated once.
+// Device word the probes write only if their XOR of the data hits one value;
+// one per device (allocated on first use, on the current device).
 static hipError_t probe_sink(uint32_t **out) {
-    static uint32_t *sink = nullptr;
+    static std::map<int, uint32_t *> sinks;
     static std::mutex sink_mu;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> g(sink_mu);
+    uint32_t *&sink = sinks[dev];
     if (!sink) {
-        hipError_t e = hipMalloc((void **)&sink, 256);
+        e = hipMalloc((void **)&sink, 256);
         if (e != hipSuccess) {
             sink = nullptr;
             return e;
@@ -1583,8 +1588,8 @@ extern "C" dart_status dart_bandwidth_probe(void *dst, const void *src, uint64_t
         return fail(DART_E_INVAL, "bad probe arguments");
     hipStream_t stream = (hipStream_t)hip_stream;
     if (!dst) {
-        // read-only: the sink is never written for finite inputs, but it must
-        // be valid device memory
+        // read-only: the loads feed an XOR that is stored only if it hits one
+        // value (so the compiler keeps them); the sink must be valid memory
         uint32_t *sink = nullptr;
         HIP_TRY(probe_sink(&sink), "hipMalloc(probe sink)");
         const uint64_t n = bytes / 16;
