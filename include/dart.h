@@ -309,9 +309,14 @@ typedef struct {
 } dart_tuning;
 
 /* Times the batched kernel on the given views over candidate tile shapes,
- * occupancies, tile orders and (if rebrick != 0) brick shapes, and keeps the
- * fastest for later dart_render_batch calls on these stacks.  best_out and
- * best_ms_out are nullable. */
+ * occupancies, tile orders, orientations and (if rebrick != 0) brick shapes,
+ * then over cells per batch and depth sync for the chosen shape, and keeps the
+ * fastest for later dart_render_batch calls on these stacks (candidates within
+ * 2% of the fastest count as ties; the first in the sweep wins).  Errors:
+ * DART_E_INVAL for bad arguments, or for labelled or vector stacks with
+ * rebrick != 0; a HIP failure is returned as such, and the stacks are then
+ * marked untuned (their renders use the process-wide dart_set_tuning shape).
+ * best_out and best_ms_out are nullable. */
 dart_status dart_autotune(dart_stack *const *stacks, const dart_view *views, int32_t n,
                           int32_t rebrick, dart_tuning *best_out, double *best_ms_out,
                           void *hip_stream);
