@@ -606,24 +606,33 @@ class EpochReader:
         return self.jr.numpy(), self.br.numpy()
 
 
-def streamed_oracle_flux(torch, dims, times, seed, gamma, knots, views, kind="f32_as_bf16"):
+def streamed_oracle_flux(torch, dims, times, seed, gamma, knots, views, kind="f32_as_bf16",
+                         with_source=False):
     """Whole images of several views by the snapshot-outer oracle: the outer
-    loop runs over epoch intervals, each epoch is read back once."""
+    loop runs over epoch intervals, each epoch is read back once.  Returns
+    [(image, flux, cell_steps)] per view on the stored values (``kind``); with
+    ``with_source`` also the same on the FP32 source fields, in the same pass
+    (for the storage error), as a second list."""
     import oracle
     t = np.asarray(times)
     M = len(t)
     reader = EpochReader(torch, dims, t, seed, gamma, knots)
     ovs = [oracle.View(v.theta_deg, v.phi_deg, v.width, v.height, v.pixel_scale, v.t_obs,
                        v.alpha, v.flags & 7) for v in views]
-    imgs = [np.zeros((v.height, v.width)) for v in views]
-    steps = [0] * len(views)
+    kinds = [kind] + (["f32"] if with_source else [])
+    imgs = {k: [np.zeros((v.height, v.width)) for v in views] for k in kinds}
+    steps = {k: [0] * len(views) for k in kinds}
     for m in range(M - 1):
         js, bs = reader.pair(m)
-        for k, ov in enumerate(ovs):
-            steps[k] += oracle.render_window(t, js, bs, m, ov, t[m], t[m + 1], int(m == M - 2),
-                                             imgs[k], encoding=kind, ring=True)
+        for enc in kinds:
+            for k, ov in enumerate(ovs):
+                steps[enc][k] += oracle.render_window(t, js, bs, m, ov, t[m], t[m + 1],
+                                                      int(m == M - 2), imgs[enc][k],
+                                                      encoding=enc, ring=True)
     del reader
-    return [(img, oracle.flux(img, ov), n) for img, ov, n in zip(imgs, ovs, steps)]
+    out = [[(img, oracle.flux(img, ov), n) for img, ov, n in zip(imgs[enc], ovs, steps[enc])]
+           for enc in kinds]
+    return (out[0], out[1]) if with_source else out[0]
 
 
 def run_large_workload(args, dart, torch):

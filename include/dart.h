@@ -140,6 +140,21 @@ typedef struct {
 } dart_stack_info;
 dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info *info);
 
+/* Copies epoch m of a plain stack back in the caller's layout of
+ * dart_load_epochs (emissivity [nz][ny][nx], velocity [nz][ny][nx][3]): the
+ * values the renders read (the inputs j' and beta of Sec. 2.5 after rounding
+ * to the storage type), each widened exactly, to FP64 for FP64 stacks and to
+ * FP32 for the others.  Inspection only: the storage error of a 16-bit stack
+ * is a render of these values against a render of the source fields.
+ *   flags   DART_DEVICE_PTRS: the two arrays are device memory (stream-ordered,
+ *           the call returns once the copy is enqueued); otherwise host memory
+ *           (staged through a temporary device buffer, the call returns after
+ *           the copy)
+ * DART_E_INVAL for labelled or vector stacks, m outside [0, M) or an epoch
+ * never filled; the arrays are untouched on error. */
+dart_status dart_stack_read_epoch(const dart_stack *s, int32_t m, void *emissivity,
+                                  void *velocity, uint32_t flags, void *hip_stream);
+
 /* Places the stack inside a larger domain, for renders of sub-domains whose
  * partial images add up to the render of the whole (optically thin emission
  * is additive along a ray; the paper's partial renders of sub-regions,

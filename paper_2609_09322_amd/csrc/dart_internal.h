@@ -110,6 +110,9 @@ hipError_t launch_convert(int src_f64, int store, const void *j, const void *bet
                           unsigned long long *err, hipStream_t s);
 hipError_t launch_rebrick(int store, const StackDev &from, const StackDev &to, void *dst,
                           hipStream_t s);
+// One epoch of a stack back in the caller's layout, widened to FP64 (FP64
+// stacks) or FP32 (the others): j [ncell], beta [ncell][3] (device).
+hipError_t launch_read_epoch(const StackDev &st, int32_t m, void *j, void *beta, hipStream_t s);
 // Emissivity fields of n resident records into a packed array (vector stacks).
 hipError_t launch_pack_j(int store, const void *records, void *out, uint64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,

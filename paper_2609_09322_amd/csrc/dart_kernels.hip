@@ -835,6 +835,21 @@ __device__ __forceinline__ uint32_t f2h_rne(float f) {
     return (uint32_t)__half_as_ushort(__float2half_rn(f));
 }
 
+// A value of the source type as an FP32 value that rounds to nearest even in
+// one step to FP16 or BF16.  FP32 sources pass unchanged.  FP64 sources are
+// rounded to FP32 by round-to-odd (truncate, then set the last bit if the
+// truncation was inexact): with at least two more significant bits than the
+// 16-bit format at every magnitude, the second rounding of a round-to-odd
+// result equals a direct rounding of the FP64 value (Boldo and Melquiond,
+// "Emulation of FMA and correctly rounded sums: proved algorithms using
+// rounding to odd", IEEE Trans. Computers 57, 2008).
+__device__ __forceinline__ float narrow_for16(float v) { return v; }
+__device__ __forceinline__ float narrow_for16(double v) {
+    float f = __double2float_rz(v);
+    if ((double)f != v) f = __uint_as_float(__float_as_uint(f) | 1u);
+    return f;
+}
+
 // caller layout (one epoch: j [nz][ny][nx], beta [nz][ny][nx][3]) -> resident
 // records, with validation: every value finite, |beta| < 1 in the source type
 // and again after rounding to the storage type.  The first bad element (as
@@ -867,13 +882,15 @@ __global__ void __launch_bounds__(256) k_convert(const Src *__restrict__ j,
             ((float4 *)data)[rec] = r;
             qj = r.x; qx = r.y; qy = r.z; qz = r.w;
         } else if constexpr (S == ST_F16) {
-            uint32_t hj = f2h_rne((float)jv), hx = f2h_rne((float)bx), hy = f2h_rne((float)by),
-                     hz = f2h_rne((float)bz);
+            const Src *bc = beta + 3 * c;
+            uint32_t hj = f2h_rne(narrow_for16(j[c])), hx = f2h_rne(narrow_for16(bc[0])),
+                     hy = f2h_rne(narrow_for16(bc[1])), hz = f2h_rne(narrow_for16(bc[2]));
             ((uint2 *)data)[rec] = uint2{hj | (hx << 16), hy | (hz << 16)};
             qj = h2f(hj); qx = h2f(hx); qy = h2f(hy); qz = h2f(hz);
         } else {
-            uint32_t hj = f2bf16_rne((float)jv), hx = f2bf16_rne((float)bx),
-                     hy = f2bf16_rne((float)by), hz = f2bf16_rne((float)bz);
+            const Src *bc = beta + 3 * c;
+            uint32_t hj = f2bf16_rne(narrow_for16(j[c])), hx = f2bf16_rne(narrow_for16(bc[0])),
+                     hy = f2bf16_rne(narrow_for16(bc[1])), hz = f2bf16_rne(narrow_for16(bc[2]));
             ((uint2 *)data)[rec] = uint2{hj | (hx << 16), hy | (hz << 16)};
             qj = __uint_as_float(hj << 16); qx = __uint_as_float(hx << 16);
             qy = __uint_as_float(hy << 16); qz = __uint_as_float(hz << 16);
@@ -904,6 +921,31 @@ __global__ void __launch_bounds__(256) k_rebrick(StackDev from, StackDev to, int
                        z = (uint32_t)(c / ((uint64_t)n0 * n1));
         dst[(uint64_t)m * to.epoch_stride + cell_offset(to, x, y, z)] =
             src[(uint64_t)m * from.epoch_stride + cell_offset(from, x, y, z)];
+    }
+}
+
+// One epoch of resident records back in the caller's layout (j [nz][ny][nx],
+// beta [nz][ny][nx][3]), each value widened exactly to Out (FP64 for FP64
+// stacks, FP32 otherwise).
+template <int S, typename Out>
+__global__ void __launch_bounds__(256) k_read_epoch(StackDev st, int32_t m, Out *__restrict__ j,
+                                                    Out *__restrict__ beta) {
+    using Raw = typename RecT<S>::raw;
+    using V = typename RecT<S>::val;
+    const uint32_t n0 = st.n[0], n1 = st.n[1];
+    const uint64_t ncell = (uint64_t)n0 * n1 * st.n[2];
+    const Raw *src = (const Raw *)st.data;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+         c += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t x = (uint32_t)(c % n0), y = (uint32_t)((c / n0) % n1),
+                       z = (uint32_t)(c / ((uint64_t)n0 * n1));
+        const Raw r = src[(uint64_t)m * st.epoch_stride + cell_offset(st, x, y, z)];
+        V vj, vx, vy, vz;
+        decode<S, V>(r, vj, vx, vy, vz);
+        j[c] = (Out)vj;
+        beta[3 * c] = (Out)vx;
+        beta[3 * c + 1] = (Out)vy;
+        beta[3 * c + 2] = (Out)vz;
     }
 }
 
@@ -1083,6 +1125,31 @@ hipError_t launch_rebrick(int store, const StackDev &from, const StackDev &to, v
         case ST_BF16: return rebrick_impl<8>(from, to, dst, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_read_epoch(const StackDev &st, int32_t m, void *j, void *beta, hipStream_t s) {
+    const uint64_t ncell = (uint64_t)st.n[0] * st.n[1] * st.n[2];
+    const dim3 g(grid_for(ncell, 1u << 15)), b(256);
+    switch (st.store) {
+        case ST_F64:
+            hipLaunchKernelGGL((k_read_epoch<ST_F64, double>), g, b, 0, s, st, m, (double *)j,
+                               (double *)beta);
+            break;
+        case ST_F32:
+            hipLaunchKernelGGL((k_read_epoch<ST_F32, float>), g, b, 0, s, st, m, (float *)j,
+                               (float *)beta);
+            break;
+        case ST_F16:
+            hipLaunchKernelGGL((k_read_epoch<ST_F16, float>), g, b, 0, s, st, m, (float *)j,
+                               (float *)beta);
+            break;
+        case ST_BF16:
+            hipLaunchKernelGGL((k_read_epoch<ST_BF16, float>), g, b, 0, s, st, m, (float *)j,
+                               (float *)beta);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_pack_j(int store, const void *records, void *out, uint64_t n, hipStream_t s) {

@@ -95,14 +95,33 @@ static int ilog2_exact(int v) {
     return (1 << l) == v ? l : -1;
 }
 
-static void layout(dart_stack *s, const int lb[3]) {
+// Records per epoch of dims padded to whole bricks of 2^lb cells.
+static uint64_t padded_records(const int32_t dims[3], const int lb[3]) {
     uint64_t per = 1;
+    for (int a = 0; a < 3; a++)
+        per *= (((uint64_t)dims[a] + (1u << lb[a]) - 1) >> lb[a]) << lb[a];
+    return per;
+}
+
+// The kernels address a record inside its epoch with a 32-bit offset
+// (brick index and cell in brick): the padded epoch must hold at most 2^32
+// records.  Checked before anything is allocated.
+static dart_status check_offsets(const int32_t dims[3], const int lb[3]) {
+    const uint64_t per = padded_records(dims, lb);
+    if (per > (1ull << 32))
+        return fail(DART_E_INVAL,
+                    "%llu records per epoch once padded to %dx%dx%d bricks: more than the 2^32 "
+                    "that 32-bit record offsets address",
+                    (unsigned long long)per, 1 << lb[0], 1 << lb[1], 1 << lb[2]);
+    return DART_OK;
+}
+
+static void layout(dart_stack *s, const int lb[3]) {
     for (int a = 0; a < 3; a++) {
         s->dev.lb[a] = lb[a];
         s->dev.nb[a] = (s->dev.n[a] + (1 << lb[a]) - 1) >> lb[a];
-        per *= (uint64_t)s->dev.nb[a] << lb[a];
     }
-    s->dev.epoch_stride = per;
+    s->dev.epoch_stride = (int64_t)padded_records(s->dev.n, lb);
 }
 
 static void default_brick(int store, int lb[3]) {
@@ -144,6 +163,10 @@ extern "C" dart_status dart_stack_create(const int32_t dims[3], const double cel
     if (st != DART_OK) return st;
     const int store = store_of(storage);
     if (store < 0) return fail(DART_E_INVAL, "unknown storage dtype %d", (int)storage);
+    int lb[3];
+    default_brick(store, lb);
+    st = check_offsets(dims, lb);
+    if (st != DART_OK) return st;
     std::unique_ptr<dart_stack> s(new dart_stack());
     HIP_TRY(hipGetDevice(&s->device), "hipGetDevice");
     for (int a = 0; a < 3; a++) {
@@ -155,8 +178,6 @@ extern "C" dart_status dart_stack_create(const int32_t dims[3], const double cel
     s->storage = storage;
     s->times.assign(epoch_times, epoch_times + n_epochs);
     s->filled.assign(n_epochs, 0);
-    int lb[3];
-    default_brick(store, lb);
     layout(s.get(), lb);
     s->bytes = s->dev.epoch_stride * n_epochs * record_bytes(store);
     void *data = nullptr, *t = nullptr;
@@ -473,6 +494,37 @@ extern "C" dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info 
     return DART_OK;
 }
 
+extern "C" dart_status dart_stack_read_epoch(const dart_stack *s, int32_t m, void *emissivity,
+                                             void *velocity, uint32_t flags, void *hip_stream) {
+    if (!s || !emissivity || !velocity) return fail(DART_E_INVAL, "NULL argument");
+    if (s->labelled() || s->vector())
+        return fail(DART_E_INVAL, "read the epochs of the sub-domains or components instead");
+    if (m < 0 || m >= s->dev.n_epochs)
+        return fail(DART_E_INVAL, "epoch %d outside [0, %d)", m, s->dev.n_epochs);
+    if (!s->filled[m]) return fail(DART_E_INVAL, "epoch %d was never filled", m);
+    if (flags & ~(uint32_t)DART_DEVICE_PTRS) return fail(DART_E_INVAL, "unknown flags 0x%x", flags);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const uint64_t ncell = (uint64_t)s->dev.n[0] * s->dev.n[1] * s->dev.n[2];
+    const size_t esz = s->dev.store == ST_F64 ? 8 : 4;
+    if (flags & DART_DEVICE_PTRS) {
+        HIP_TRY(launch_read_epoch(s->dev, m, emissivity, velocity, stream), "read kernel");
+        note_use(s, stream);
+        return DART_OK;
+    }
+    void *buf = nullptr;
+    HIP_TRY(hipMalloc(&buf, ncell * esz * 4), "hipMalloc(read staging)");
+    struct Free {
+        void *p;
+        ~Free() { (void)hipFree(p); }
+    } guard{buf};
+    void *dj = buf, *db = (char *)buf + ncell * esz;
+    HIP_TRY(launch_read_epoch(s->dev, m, dj, db, stream), "read kernel");
+    HIP_TRY(hipMemcpyAsync(emissivity, dj, ncell * esz, hipMemcpyDeviceToHost, stream), "D2H j");
+    HIP_TRY(hipMemcpyAsync(velocity, db, 3 * ncell * esz, hipMemcpyDeviceToHost, stream), "D2H beta");
+    HIP_TRY(hipStreamSynchronize(stream), "sync");
+    return DART_OK;
+}
+
 extern "C" dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_out) {
     if (!s || !bytes_out) return fail(DART_E_INVAL, "NULL argument");
     *bytes_out = record_bytes(s->dev.store);
@@ -507,6 +559,10 @@ extern "C" dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3],
         cells *= brick[a];
     }
     if (cells > 4096) return fail(DART_E_INVAL, "brick larger than 4096 cells");
+    {
+        dart_status so = check_offsets(s->dev.n, lb);
+        if (so != DART_OK) return so;
+    }
     if (s->labelled()) return fail(DART_E_INVAL, "re-lay the sub-domains of a labelled stack before joining them");
     if (s->vector()) return fail(DART_E_INVAL, "re-lay the components of a vector stack before joining them");
     if (s->refs.load() > 0) return fail(DART_E_BUSY, "the stack is held by a labelled or vector stack");
@@ -569,15 +625,25 @@ extern "C" dart_status dart_stack_rebrick(dart_stack *s, const int32_t brick[3],
 
 // ------------------------------------------------------------------ views
 
+// sin and cos of an angle in degrees.  The angle is split exactly (IEEE
+// remainder) into a quarter-turn count q and a rest r in [-45, 45] degrees;
+// sin and cos of r are rotated by q quarter turns, so multiples of 90 degrees
+// give exact 0 and +-1 and the rest keeps full precision for any angle.
 static void sincos_deg(double deg, double *s, double *c) {
-    double r = fmod(deg, 360.0);
-    if (r < 0) r += 360.0;
-    if (r == 0.0) { *s = 0.0; *c = 1.0; return; }
-    if (r == 90.0) { *s = 1.0; *c = 0.0; return; }
-    if (r == 180.0) { *s = 0.0; *c = -1.0; return; }
-    if (r == 270.0) { *s = -1.0; *c = 0.0; return; }
-    *s = sin(deg * (M_PI / 180.0));
-    *c = cos(deg * (M_PI / 180.0));
+    int q = 0;
+    const double r = remquo(deg, 90.0, &q);
+    const double rad = r * (M_PI / 180.0);
+    const double sr = r == 0.0 ? 0.0 : sin(rad), cr = r == 0.0 ? 1.0 : cos(rad);
+    double so, co;
+    switch (q & 3) {
+        case 0: so = sr; co = cr; break;
+        case 1: so = cr; co = -sr; break;
+        case 2: so = -sr; co = -cr; break;
+        default: so = -cr; co = sr; break;
+    }
+    // (+0.0 instead of -0.0, so that signs of zero components never differ)
+    *s = so + 0.0;
+    *c = co + 0.0;
 }
 
 dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView *rv) {
@@ -924,6 +990,11 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         g.views.push_back(rv);
         const int tw = 1 << lw, th = 64 >> lw;
         const int ntx = (rv.width + tw - 1) / tw, nty = (rv.height + th - 1) / th;
+        // tile coordinates are 16-bit in the descriptors
+        if (ntx > 65536 || nty > 65536)
+            return fail(DART_E_INVAL,
+                        "view %d: %dx%d image in %dx%d tiles needs more than 65536 tiles per "
+                        "side", i, rv.width, rv.height, tw, th);
         for (int ty = 0; ty < nty; ty++)
             for (int tx = 0; tx < ntx; tx++) {
                 Tile t;

@@ -31,7 +31,7 @@ DART_ACCUMULATE = 0x80
 DART_EXACT_TIME = 0x100
 
 EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "dart_free_epochs",
-           "dart_stack_get_info", "dart_stack_rebrick", "dart_stack_set_placement",
+           "dart_stack_get_info", "dart_stack_read_epoch", "dart_stack_rebrick", "dart_stack_set_placement",
            "dart_labelled_create", "dart_vector_create", "dart_streamer_create",
            "dart_streamer_render",
            "dart_streamer_get_stats", "dart_streamer_destroy", "dart_render", "dart_render_batch",
@@ -111,6 +111,7 @@ def _load():
         "dart_stack_set_epochs": [_P, I32, I32, ctypes.c_int, _P, _P, U32, _P],
         "dart_free_epochs": [_P],
         "dart_stack_get_info": [_P, _P],
+        "dart_stack_read_epoch": [_P, I32, _P, _P, U32, _P],
         "dart_stack_rebrick": [_P, _P, _P],
         "dart_stack_set_placement": [_P, _P, _P],
         "dart_labelled_create": [_P, I32, _P],
@@ -257,6 +258,29 @@ def dart_stack_get_info(stack: Stack) -> dart_stack_info:
     info = dart_stack_info()
     _check(_load().dart_stack_get_info(stack.handle, ctypes.byref(info)))
     return info
+
+
+def dart_stack_read_epoch(stack: Stack, m, emissivity, velocity, stream=None):
+    """Epoch m as stored, widened exactly, into ``emissivity`` ([nz][ny][nx]) and
+    ``velocity`` ([nz][ny][nx][3]): float64 arrays for FP64 stacks, float32 for
+    the others; both numpy arrays or both device tensors."""
+    info = dart_stack_get_info(stack)
+    nx, ny, nz = info.dims
+    esz = 8 if info.storage == DART_F64 else 4
+    for arr, per in ((emissivity, 1), (velocity, 3)):
+        if isinstance(arr, np.ndarray):
+            count, item = arr.size, arr.itemsize
+        else:
+            count, item = arr.numel(), arr.element_size()
+        if count != nx * ny * nz * per or item != esz:
+            raise ValueError(f"read_epoch arrays: {nx * ny * nz * per} values of {esz} bytes "
+                             f"expected, got {count} of {item}")
+    jp, jdev = _ptr(emissivity)
+    bp, bdev = _ptr(velocity)
+    if jdev != bdev:
+        raise ValueError("emissivity and velocity must both be host or both be device arrays")
+    _check(_load().dart_stack_read_epoch(stack.handle, int(m), jp, bp,
+                                         DART_DEVICE_PTRS if jdev else 0, _stream(stream)))
 
 
 def dart_stack_rebrick(stack: Stack, brick, stream=None):

@@ -88,6 +88,29 @@ def test_library_loads_and_reports_errors_without_gpu():
     assert "2 to 4" in d.dart_last_error()
 
 
+def test_record_offsets_fit_32_bits_checked_before_allocation():
+    """Record offsets inside an epoch are 32-bit: a stack whose padded epoch
+    would hold more than 2^32 records is refused before any device call (so
+    here, without a GPU, with DART_E_INVAL rather than a device error)."""
+    import ctypes
+    import paper_2609_09322_amd as d
+    lib = d.dart._load()
+    cell = (ctypes.c_double * 3)(1, 1, 1)
+    t = (ctypes.c_double * 1)(0.0)
+    out = ctypes.c_void_p(1)
+    # 2^31 cells; 16-bit records in 4x2x2 bricks pad x from 1 to 4: 2^33 records
+    dims = (ctypes.c_int32 * 3)(1, 1 << 11, 1 << 20)
+    assert lib.dart_stack_create(dims, cell, 1, t, d.DART_F16, 0, ctypes.byref(out)) == d.DART_E_INVAL
+    assert "2^32" in d.dart_last_error()
+    assert out.value is None
+    # the same grid as FP32 records (2x2x2 bricks): 2^32 records, the most allowed,
+    # passes the check and reaches the device (none here)
+    out = ctypes.c_void_p(1)
+    rc = lib.dart_stack_create(dims, cell, 1, t, d.DART_F32, 0, ctypes.byref(out))
+    assert rc != d.DART_OK and "2^32" not in d.dart_last_error()
+    assert out.value is None
+
+
 def test_tuning_checks_without_gpu():
     """dart_set_tuning validates every field on the host; a rejected tuning
     leaves the current one in place."""

@@ -6,8 +6,9 @@ kernel replayed from a captured graph).
   the four images against the FP64 oracle (<= 1e-5), total flux (<= 1e-6).
 * uneven batch, 384^3, 32 epochs, FP16 and BF16, 64 isotropic views with
   sides in {128, 256, 512, 1024} rendered by one batched call: the first 8
-  views checked, whole images (flux too) up to 256^2 and 2048 sampled pixels
-  above, against the oracle on the stored (rounded) values (<= 2e-3).
+  views and the first 1024^2 view checked whole (every pixel <= 2e-3, flux
+  <= 1e-6, cell-steps) against the oracle on the stored (rounded) values,
+  with the storage error against the FP32 source fields printed beside.
 * served mix: requests on several resident FP16 stacks submitted to the
   continuous-batching server under a tight memory budget; every served image
   is bit-identical to a solo render of the same request.
@@ -83,7 +84,12 @@ def test_jet_workload_every_pixel(env):
 
 
 @pytest.mark.parametrize("kind", ["f16", "bf16"])
-def test_uneven_batch_sampled_images(env, kind):
+def test_uneven_batch_checked_images(env, kind):
+    """The 64-view batch in one call; the first 8 views (the seeded sample)
+    and the first 1024^2 view are checked whole: every pixel within 2e-3 of
+    the oracle on the stored values, flux within 1e-6, cell-steps within 1e-5.
+    The storage error (the oracle on the stored values against the oracle on
+    the FP32 source fields) is printed for each, not graded."""
     dart, torch = env
     dims, M = (384, 384, 384), 32
     j, b, times = synth.jet_torch(dims, M, 3, gamma_spine=5.0, n_knots=4)
@@ -91,6 +97,7 @@ def test_uneven_batch_sampled_images(env, kind):
     storage = dart.DART_F16 if kind == "f16" else dart.DART_BF16
     st = dart.dart_load_epochs(dims, (1, 1, 1), times, j, b, storage)
     jh, bh = _host_16bit(j, b, kind)
+    js, bs = j.cpu().numpy(), b.cpu().numpy()
     del j, b
     torch.cuda.empty_cache()
     L = synth.diag(dims)
@@ -101,25 +108,24 @@ def test_uneven_batch_sampled_images(env, kind):
     imgs = [torch.zeros((v.height, v.width), dtype=torch.float32, device="cuda") for v in views]
     flux, steps = dart.dart_render_batch([st] * 64, views, imgs, stream=stream)
     ost = oracle.Stack(jh, bh, times, encoding=kind)
-    rng = np.random.default_rng(17)
-    for k in range(8):
+    src = oracle.Stack(js, bs, times)
+    checked = list(range(8)) + [next(k for k, v in enumerate(views) if v.width == 1024)]
+    for k in checked:
         v = views[k]
         ov = oracle.View(v.theta_deg, v.phi_deg, v.width, v.height, v.pixel_scale, 0.0, 0.6, 0)
         got = imgs[k].cpu().numpy()
-        if v.width <= 256:
-            ref, rsteps = oracle.render(ost, ov)
-            e = pix_err(got, ref).max()
-            assert flux[k] == pytest.approx(oracle.flux(ref, ov), rel=1e-6)
-            assert abs(int(steps[k]) - rsteps) <= 1e-5 * rsteps
-        else:
-            pix = np.stack([rng.integers(0, v.width, 2048), rng.integers(0, v.height, 2048)], axis=1)
-            ref, _ = oracle.render(ost, ov, pixels=pix)
-            floor = 1e-3 * float(np.abs(got).max())
-            gv = got[pix[:, 1], pix[:, 0]].astype(np.float64)
-            e = (np.abs(gv - ref) / np.maximum(np.abs(ref), floor)).max()
-        print(f"{kind} view {k} ({v.width}^2, theta {v.theta_deg:.1f}): max per-pixel err {e:.3e}",
-              flush=True)
+        ref, rsteps = oracle.render(ost, ov)
+        e = pix_err(got, ref).max()
+        rflux = oracle.flux(ref, ov)
+        sref, _ = oracle.render(src, ov)
+        sflux = oracle.flux(sref, ov)
+        print(f"{kind} view {k} ({v.width}^2, theta {v.theta_deg:.1f}): max per-pixel err "
+              f"{e:.3e}, flux {flux[k]:.9e} vs {rflux:.9e} ({abs(flux[k] / rflux - 1):.2e}), "
+              f"steps {steps[k]} vs {rsteps}; storage error: per pixel "
+              f"{pix_err(ref, sref).max():.3e}, flux {abs(rflux / sflux - 1):.3e}", flush=True)
         assert e <= 2e-3
+        assert flux[k] == pytest.approx(rflux, rel=1e-6)
+        assert abs(int(steps[k]) - rsteps) <= 1e-5 * rsteps
 
 
 def test_server_mix_equals_solo(env):
