@@ -255,6 +255,32 @@ dart_status dart_render_batch(const dart_stack *const *stacks, const dart_view *
                               void *const *images, double *flux_out, uint64_t *steps_out,
                               void *hip_stream);
 
+/* The batched render for callers that cannot allocate device memory: code
+ * under stream capture, tight serving loops, hosts that forbid hipMalloc.
+ * Same arguments, plan, kernels and results as dart_render_batch (pixels and
+ * cell-steps identical; flux equal up to the order of the FP64 atomic
+ * additions that sum it), but its accumulators and view / tile
+ * descriptors live in a fixed array of DART_NOALLOC_SCRATCH_BYTES of device
+ * memory that the library holds on each GPU it runs on until the process
+ * ends.  The call makes no hipMalloc, hipFree or pinned-host allocation.
+ *   images     device memory only: every view needs DART_DEVICE_PTRS
+ *              (DART_KERNEL_PLAIN is refused)
+ *   flux_out, steps_out  nullable host arrays [n]; when given, the call waits
+ *              for the stream
+ * The call uploads the descriptors with a pageable copy and waits for the
+ * stream once before launching, so it returns after earlier work on the
+ * stream has finished; without flux_out / steps_out it returns once the
+ * render is enqueued.  A batch whose accumulators and descriptors (2n + 4
+ * words per launch group, then 384 bytes per view and 8 per 64-pixel
+ * tile) exceed the scratch returns DART_E_INVAL before anything is enqueued.
+ * Every call on one GPU shares that GPU's scratch and overwrites what the last
+ * call left there: calls on one stream are ordered, but calls that overlap on
+ * one GPU from different streams or host threads race. */
+#define DART_NOALLOC_SCRATCH_BYTES (16u << 20)
+dart_status dart_render_batch_noalloc(const dart_stack *const *stacks, const dart_view *views,
+                                      int32_t n, void *const *images, double *flux_out,
+                                      uint64_t *steps_out, void *hip_stream);
+
 /* ------------------------------------------------------------- streaming --
  * Out-of-core rendering (Sec. 4, Fig. 5: snapshot by snapshot into one image
  * buffer per camera; Sec. 5.2 and 6.2: data larger than device memory, and

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdart.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["dart_kernels.hip", "dart_runtime.hip", "dart_server.hip", "dart_stream.hip"]
+SOURCES = ["dart_kernels.hip", "dart_runtime.hip", "dart_server.hip", "dart_stream.hip",
+           "dart_noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-result",
          # no packed FP32 instructions anywhere in the device code

@@ -35,7 +35,7 @@ EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "da
            "dart_labelled_create", "dart_vector_create", "dart_streamer_create",
            "dart_streamer_render",
            "dart_streamer_get_stats", "dart_streamer_destroy", "dart_render", "dart_render_batch",
-           "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples", "dart_count_lines",
+           "dart_render_batch_noalloc", "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples", "dart_count_lines",
            "dart_record_bytes", "dart_bandwidth_probe", "dart_gather_probe", "dart_server_create", "dart_submit",
            "dart_poll", "dart_wait", "dart_server_destroy", "dart_server_get_stats",
            "dart_last_error", "dart_version"]
@@ -122,6 +122,7 @@ def _load():
         "dart_streamer_destroy": [_P],
         "dart_render": [_P, _P, _P, _P, _P, _P],
         "dart_render_batch": [_P, _P, I32, _P, _P, _P, _P],
+        "dart_render_batch_noalloc": [_P, _P, I32, _P, _P, _P, _P],
         "dart_autotune": [_P, _P, I32, I32, _P, _P, _P],
         "dart_set_tuning": [_P],
         "dart_get_tuning": [_P],
@@ -355,6 +356,25 @@ def dart_render_batch(stacks, views, images, stream=None, stats=True):
     steps = np.zeros(n, dtype=np.uint64)
     _check(_load().dart_render_batch(st, vs, n, ims, flux.ctypes.data if stats else None,
                                      steps.ctypes.data if stats else None, _stream(stream)))
+    return (flux, steps) if stats else (None, None)
+
+
+def dart_render_batch_noalloc(stacks, views, images, stream=None, stats=True):
+    """dart_render_batch with its scratch in the library's fixed device array
+    (no allocation); images must be device tensors."""
+    n = len(views)
+    st = (ctypes.c_void_p * n)(*[s.handle for s in stacks])
+    vs = (dart_view * n)()
+    ims = (ctypes.c_void_p * n)()
+    for i, (v, im) in enumerate(zip(views, images)):
+        cv, ip = _view_for(v, im)
+        vs[i] = cv
+        ims[i] = ip
+    flux = np.zeros(n, dtype=np.float64)
+    steps = np.zeros(n, dtype=np.uint64)
+    _check(_load().dart_render_batch_noalloc(st, vs, n, ims, flux.ctypes.data if stats else None,
+                                             steps.ctypes.data if stats else None,
+                                             _stream(stream)))
     return (flux, steps) if stats else (None, None)
 
 
