@@ -138,18 +138,25 @@ def host_copy(j_dev, b_dev, kind):
     return jh, bh
 
 
-def make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage, kind, keep_host):
+def make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage, kind, keep_host,
+                   keep_source=False):
+    """The seeded jet stack, loaded from device-generated FP32 fields.  Returns
+    (stack, epoch times, host copy in the stored encoding or None, host copy of
+    the FP32 source fields or None)."""
     import synth
     t0 = time.time()
     j, b, times = synth.jet_torch(dims, n_epochs, seed, gamma_spine=gamma, n_knots=knots)
     torch.cuda.synchronize()
     host = host_copy(j, b, kind) if keep_host else None
+    src = None
+    if keep_source:
+        src = host if kind == "f32" else (j.cpu().numpy(), b.cpu().numpy())
     st = dart.dart_load_epochs(dims, (1.0, 1.0, 1.0), times, j, b, storage)
     torch.cuda.synchronize()
     del j, b
     torch.cuda.empty_cache()
     log(f"stack {dims} x {n_epochs} epochs ({kind}) generated and loaded in {time.time() - t0:.1f} s")
-    return st, times, host
+    return st, times, host, src
 
 
 def workload_key(args):
@@ -259,15 +266,60 @@ def pix_err(got, ref, img_max):
     return np.abs(got - ref) / np.maximum(np.abs(ref), floor)
 
 
+def whole_image_accuracy(host, src, times, views, imgs, flux, steps, idx, kind, tol):
+    """Every pixel, the flux and the cell-steps of views[idx] against the FP64
+    oracle on the stored values (the error floor from the oracle image), and
+    the storage error: the oracle on the stored values against the oracle on
+    the FP32 source fields (for 16-bit storage; zero for FP32)."""
+    import oracle
+    ost = oracle.Stack(host[0], host[1], times, encoding=kind)
+    sst = oracle.Stack(src[0], src[1], times) if (src is not None and kind != "f32") else None
+    worst = dict(pix=0.0, flux=0.0, steps=0.0, s_pix=0.0, s_flux=0.0)
+    t0 = time.perf_counter()
+    for k in idx:
+        v = views[k]
+        ov = oracle.View(v.theta_deg, v.phi_deg, v.width, v.height, v.pixel_scale, v.t_obs,
+                         v.alpha, (v.flags & 7) | (oracle.EXACT_TIME if v.flags & 0x100 else 0))
+        ref, rsteps = oracle.render(ost, ov)
+        rflux = oracle.flux(ref, ov)
+        g = imgs[k].cpu().numpy().astype(np.float64)
+        worst["pix"] = max(worst["pix"], float(pix_err(g, ref, float(np.abs(ref).max())).max()))
+        worst["flux"] = max(worst["flux"], abs(float(flux[k]) / rflux - 1.0))
+        worst["steps"] = max(worst["steps"], abs(int(steps[k]) - rsteps) / max(rsteps, 1))
+        if sst is not None:
+            sref, _ = oracle.render(sst, ov)
+            sflux = oracle.flux(sref, ov)
+            worst["s_pix"] = max(worst["s_pix"],
+                                 float(pix_err(ref, sref, float(np.abs(sref).max())).max()))
+            worst["s_flux"] = max(worst["s_flux"], abs(rflux / sflux - 1.0))
+    out = {"max_pixel_rel_err": worst["pix"], "flux_rel_err": worst["flux"],
+           "cell_steps_rel_diff": worst["steps"], "images_checked_whole": len(idx),
+           "tolerance": {"pixel": tol, "flux": 1e-6, "cell_steps": 1e-5},
+           "within_tolerance": bool(worst["pix"] <= tol and worst["flux"] <= 1e-6
+                                    and worst["steps"] <= 1e-5),
+           "against": "FP64 oracle on the stored values, every pixel of the checked images",
+           "oracle_s": time.perf_counter() - t0}
+    if kind == "f32":
+        out["storage_error"] = {"max_pixel_rel_err": 0.0, "flux_rel_err": 0.0,
+                                "note": "FP32 storage holds the FP32 source fields exactly"}
+    elif sst is not None:
+        out["storage_error"] = {"max_pixel_rel_err": worst["s_pix"], "flux_rel_err": worst["s_flux"],
+                                "against": "FP64 oracle on the FP32 source fields (reported, "
+                                           "not graded)"}
+    return out
+
+
 # --------------------------------------------------------------------------- workloads
 
 def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_spec, gamma,
                         knots, seed, rec_bytes, dtype_name, check_views=None, tune_views=None):
+    """check_views: the first check_views views are checked whole against the
+    oracle (every pixel, flux, cell-steps, storage error); None checks them all."""
     stream = torch.cuda.Stream()
     wkey = workload_key(args)
     keep_host = not args.no_cpu_baseline or args.check
-    st, times, host = make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage,
-                                     dtype_name, keep_host)
+    st, times, host, src = make_jet_stack(dart, torch, dims, n_epochs, seed, gamma, knots, storage,
+                                          dtype_name, keep_host, keep_source=args.check)
     L = math.sqrt(sum(float(d) ** 2 for d in dims))
     vflags = dart.DART_EXACT_TIME if args.exact_time else 0
     views = [dart.View(th, ph, P, P, L / P, 0.0, alpha, vflags) for th, ph, P, alpha in views_spec]
@@ -350,18 +402,17 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
                                       "device-to-host copies included"}
         log(f"host images: {hms:.3f} ms/step")
 
-    # accuracy on sampled pixels against the FP64 oracle (dequantised inputs)
+    # accuracy of whole images against the FP64 oracle (on the stored values),
+    # and the storage error (the stored values against the FP32 source fields)
     if args.check and host is not None:
-        cv = views if check_views is None else views[:check_views]
-        samp, _, _ = oracle_sample(host, times, cv, args.check_rays, 7, None, dtype_name)
-        errs = []
-        for (pix, val), im in zip(samp, imgs):
-            g = im.cpu().numpy()
-            got = g[pix[:, 1], pix[:, 0]].astype(np.float64)
-            errs.append(pix_err(got, val, float(np.abs(g).max())).max())
-        res["accuracy"] = {"max_pixel_rel_err": float(max(errs)), "sampled_pixels": int(args.check_rays),
-                           "tolerance": 1e-5 if dtype_name == "f32" else 2e-3}
-        log(f"accuracy: max per-pixel rel err {max(errs):.3e} over {args.check_rays} sampled pixels")
+        idx = list(range(n_img if check_views is None else min(check_views, n_img)))
+        acc = whole_image_accuracy(host, src, times, views, imgs, flux, steps, idx, dtype_name,
+                                   1e-5 if dtype_name == "f32" else 2e-3)
+        res["accuracy"] = acc
+        log(f"accuracy ({len(idx)} whole images): max per-pixel rel err "
+            f"{acc['max_pixel_rel_err']:.3e}, flux {acc['flux_rel_err']:.2e}, cell-steps "
+            f"{acc['cell_steps_rel_diff']:.2e}; storage error {acc.get('storage_error')}")
+    del src
 
     cpu = None
     if not args.no_cpu_baseline and host is not None:
@@ -425,7 +476,7 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
                    "images_per_step": n_img, "pixels_per_step": sum(v.width * v.height for v in views),
                    "cell_steps_per_step": cell_steps, "storage": dtype_name},
         "images_per_s": n_img / (ms_step * 1e-3),
-        "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
+        "step_ms_p50": pct(per, 50), "step_ms_p99": pct(per, 99),
         "roofline": roof, "cpu_baseline": cpu,
     }
     if "host_images" in res:
@@ -473,8 +524,61 @@ def build_stack_incremental(dart, torch, dims, n_epochs, seed, gamma, knots, sto
     return st, times
 
 
+def served_cpu_baseline(dart, torch, stacks, reqs, seconds=12.0):
+    """The oracle on random pixels of the served requests that use the 128^3 and
+    256^3 stacks (their stored values read back with dart_stack_read_epoch and
+    held as binary16 on the host; the 512^3 stacks are left out to bound host
+    memory), on every host core this process may use."""
+    import oracle
+    threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS") or 1 << 10))
+    host = {}
+    for st, n, M in stacks:
+        if n > 256:
+            continue
+        jh = np.empty((M, n, n, n), dtype=np.float16)
+        bh = np.empty((M, n, n, n, 3), dtype=np.float16)
+        jd = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+        bd = torch.empty((n, n, n, 3), dtype=torch.float32, device="cuda")
+        for m in range(M):
+            dart.dart_stack_read_epoch(st, m, jd, bd)
+            torch.cuda.synchronize()
+            jh[m] = jd.cpu().numpy().astype(np.float16)   # exact: the values are binary16
+            bh[m] = bd.cpu().numpy().astype(np.float16)
+        host[id(st)] = oracle.Stack(jh, bh, synth_times(n, M), encoding="f16")
+        del jd, bd
+    rng = np.random.default_rng(14)
+    cand = [(s, v) for s, v in reqs if id(s) in host]
+    done_steps, secs, rays = 0, 0.0, 0
+    while secs < seconds and cand:
+        s, v = cand[int(rng.integers(0, len(cand)))]
+        pix = np.stack([rng.integers(0, v.width, 4096), rng.integers(0, v.height, 4096)],
+                       axis=1).astype(np.int32)
+        ov = oracle.View(v.theta_deg, v.phi_deg, v.width, v.height, v.pixel_scale, v.t_obs,
+                         v.alpha, v.flags & 7)
+        t0 = time.perf_counter()
+        _, n_steps = oracle.render(host[id(s)], ov, pixels=pix, threads=threads)
+        secs += time.perf_counter() - t0
+        done_steps += n_steps
+        rays += len(pix)
+    return {"value": done_steps / max(secs, 1e-9), "unit": "cell-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{rays} random pixels of served requests on the 128^3 and 256^3 stacks "
+                      f"({done_steps} cell-steps, {secs:.1f} s)",
+            "cpu_model": cpu_model()}
+
+
+def synth_times(n, M):
+    import synth
+    return synth.jet_times((n, n, n), M)
+
+
 def run_serve_workload(args, dart, torch):
-    """Poisson request stream on resident FP16 stacks through the server."""
+    """Poisson request stream on resident FP16 stacks through the server.
+
+    Latency runs from each request's scheduled arrival to its completion: the
+    submitter sleeps until the arrival time, submits at once (every request has
+    its own output image, so it never waits for a buffer) and charges any
+    lateness of the submission to the request."""
     import synth
     rng = np.random.default_rng(1004)
     specs = [(128, 8), (128, 32), (256, 16), (256, 32), (512, 8), (512, 32)]
@@ -497,62 +601,76 @@ def run_serve_workload(args, dart, torch):
         reqs.append((s, dart.View(th, float(rng.uniform(0, 360)), P, P,
                                   math.sqrt(3.0) * n / P, 0.0, float(rng.uniform(0.5, 1.0)))))
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
-    pool = {P: [torch.empty((P, P), dtype=torch.float32, device="cuda") for _ in range(48)]
-            for P in sizes}
-    owner = {}
+    imgs = [torch.zeros((v.height, v.width), dtype=torch.float32, device="cuda") for _, v in reqs]
     srv = dart.dart_server_create(args.budget_gb << 30, max_inflight=512, n_streams=3)
 
-    def stream_run(arr):
-        tickets, results = [], {}
+    def timeline_delta(a, b):
+        w = max(1, b.waves_timed - a.waves_timed)
+        out = {"waves": int(b.waves_timed - a.waves_timed)}
+        for f in ("plan_ms", "enqueue_ms", "callback_to_retire_ms", "device_ms", "kernel_ms",
+                  "stream_idle_ms"):
+            out[f + "_per_wave"] = (getattr(b, f) - getattr(a, f)) / w
+        out["kernel_ms_total"] = b.kernel_ms - a.kernel_ms
+        return out
+
+    def stream_run(arr, count):
+        tickets, late = [], []
         start = time.perf_counter()
-        for q, (s, v) in enumerate(reqs[:len(arr)]):
-            slot = (v.width, q % 48)
-            if slot in owner and owner[slot] not in results:
-                results[owner[slot]] = dart.dart_wait(srv, owner[slot])
-            delay = start + arr[q] - time.perf_counter()
+        for q in range(count):
+            s, v = reqs[q]
+            due = start + arr[q]
+            delay = due - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
-            t = dart.dart_submit(srv, s, v, pool[v.width][q % 48])
-            owner[slot] = t
-            tickets.append(t)
-        for t in tickets:
-            if t not in results:
-                results[t] = dart.dart_wait(srv, t)
-        return tickets, results, time.perf_counter() - start
+            late.append(time.perf_counter() - due)
+            tickets.append(dart.dart_submit(srv, s, v, imgs[q]))
+        results = [dart.dart_wait(srv, t) for t in tickets]
+        return results, np.asarray(late) * 1e3, time.perf_counter() - start
 
-    tickets, results, wall = stream_run(arrivals)
-    lat = np.array([results[t][2] for t in tickets[warm:]])
-    steps_served = sum(results[t][1] for t in tickets[warm:])
+    tl0 = dart.dart_server_get_timeline(srv)
+    results, late_ms, wall = stream_run(arrivals, n_req)
+    tl1 = dart.dart_server_get_timeline(srv)
+    lat_submit = np.array([r[2] for r in results[warm:]])
+    lat = late_ms[warm:] + lat_submit
+    steps_served = sum(r[1] for r in results[warm:])
     span = arrivals[-1] - arrivals[warm]
-    log(f"served {n_req} requests at {rate}/s: p50 {np.percentile(lat, 50):.2f} ms, "
-        f"p99 {np.percentile(lat, 99):.2f} ms")
+    log(f"served {n_req} requests at {rate}/s: from arrival p50 {np.percentile(lat, 50):.2f} ms, "
+        f"p99 {np.percentile(lat, 99):.2f} ms (submission late by at most {late_ms.max():.2f} ms)")
     stats = dart.dart_server_get_stats(srv)
-    # saturation: every request offered at once
-    owner.clear()
+    # every served image against its solo render (the plain kernel, alone)
+    torch.cuda.synchronize()
+    same, checked = 0, 0
+    for q in range(n_req):
+        s, v = reqs[q]
+        solo = torch.empty_like(imgs[q])
+        dart.dart_render(s, v, solo, stats=False)
+        same += int(torch.equal(solo, imgs[q]))
+        checked += 1
+    torch.cuda.synchronize()
+    log(f"served images equal to their solo renders: {same} of {checked}")
+    # saturation: the first sat_n requests offered at once
     sat_n = min(1000, n_req)
-    tk, res, sat_wall = stream_run(np.zeros(sat_n))
-    sat_steps = sum(res[t][1] for t in tk)
+    tl2 = dart.dart_server_get_timeline(srv)
+    sres, _, sat_wall = stream_run(np.zeros(sat_n), sat_n)
+    tl3 = dart.dart_server_get_timeline(srv)
+    sat_steps = sum(r[1] for r in sres)
     dart.dart_server_destroy(srv)
     # plain kernel, one request after the other, on the same requests
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     p0 = time.perf_counter()
-    for q, (s, v) in enumerate(reqs[:sat_n]):
-        dart.dart_render(s, v, pool[v.width][q % 48], stream=stream, stats=False)
+    for q in range(sat_n):
+        s, v = reqs[q]
+        dart.dart_render(s, v, imgs[q], stream=stream, stats=False)
     torch.cuda.synchronize()
     plain_wall = time.perf_counter() - p0
-    # each served result equals its solo render (sampled requests)
-    same = True
-    for q in rng.choice(sat_n, size=min(32, sat_n), replace=False):
+    # compulsory bytes of the saturation requests (8-byte FP16 records + images)
+    comp = 0
+    for q in range(sat_n):
         s, v = reqs[q]
-        a = torch.zeros((v.height, v.width), dtype=torch.float32, device="cuda")
-        b = torch.zeros_like(a)
-        srv2 = dart.dart_server_create(1 << 30, 4, 1)
-        dart.dart_wait(srv2, dart.dart_submit(srv2, s, v, a))
-        dart.dart_server_destroy(srv2)
-        dart.dart_render(s, v, b, stats=False)
-        torch.cuda.synchronize()
-        same &= bool(torch.equal(a, b))
+        comp += dart.dart_count_samples(s, v, stream) * 8 + 4 * v.width * v.height
+    achieved = comp / sat_wall / 1e9
+    cpu = None if args.no_cpu_baseline else served_cpu_baseline(dart, torch, stacks, reqs)
     return {
         "metric": "cell-steps/s & images/s (batched vs plain kernel) at 1e-5 rel; p50/p99 ms",
         "value": sat_steps / sat_wall, "unit": "cell-steps/s", "n_gpus": 1,
@@ -563,13 +681,31 @@ def run_serve_workload(args, dart, torch):
                                "(128^3..512^3, 8-32 epochs), images 128^2..1024^2" % rate,
                    "requests": n_req, "resident_gb": resident / 1e9, "budget_gb": args.budget_gb},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "latency_definition": "scheduled arrival to completion (the completion callback of the "
+                              "request's wave), after the first %d requests" % warm,
+        "latency_from_submit_ms": {"p50": float(np.percentile(lat_submit, 50)),
+                                   "p99": float(np.percentile(lat_submit, 99))},
+        "submission_late_ms_max": float(late_ms.max()),
         "offered_req_per_s": rate, "served_req_per_s": (n_req - warm) / max(span, 1e-9),
         "served_cell_steps_per_s": steps_served / max(span, 1e-9),
         "saturation_images_per_s": sat_n / sat_wall,
+        "saturation_cell_steps_per_s": sat_steps / sat_wall,
         "plain_images_per_s": sat_n / plain_wall,
         "speedup_images_per_s_vs_plain": plain_wall / sat_wall,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "traffic_source": "no counter run of the served mix",
+                     "bytes_per_launch": None,
+                     "bytes_definition": "compulsory bytes of the %d saturation requests "
+                                         "(distinct positive-weight records x 8 B + images) over "
+                                         "their wall time, host scheduling included" % sat_n},
         "waves": int(stats.waves), "max_wave_requests": int(stats.max_wave_requests),
-        "served_equals_solo": same,
+        "timeline_poisson": timeline_delta(tl0, tl1),
+        "timeline_saturation": timeline_delta(tl2, tl3),
+        "served_equals_solo": {"identical": same, "checked": checked,
+                               "note": "each image served in the Poisson mix against the same "
+                                       "request rendered alone by the plain kernel, bit for bit"},
+        "cpu_baseline": cpu,
     }
 
 
@@ -717,7 +853,7 @@ def run_large_workload(args, dart, torch):
         "config": {"workload": f"large: 512x512x2048, 40 epochs, BF16 ({info.device_bytes / 1e9:.1f} GB "
                                f"resident), {n} views at 1024^2, FP64 ray parameters, Kahan",
                    "cell_steps_per_step": cell_steps},
-        "images_per_s": n / (ms_step * 1e-3), "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
+        "images_per_s": n / (ms_step * 1e-3), "step_ms_p50": pct(per, 50), "step_ms_p99": pct(per, 99),
         "plain": {"ms_per_step": pms, "images_per_s": n / (pms * 1e-3)},
         "speedup_images_per_s_vs_plain": pms / ms_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -881,7 +1017,7 @@ def run_labelled_workload(args, dart, torch):
         "config": {"workload": "labelled: jet 256x256x512, 16 epochs, FP32, core refined 2x "
                                "(7 sub-domains), 4 views 512^2", "sub_domains": len(parts),
                    "resident_gb": gb, "cell_steps_per_step": cell_steps},
-        "images_per_s": 4 / (ms_step * 1e-3), "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
+        "images_per_s": 4 / (ms_step * 1e-3), "step_ms_p50": pct(per, 50), "step_ms_p99": pct(per, 99),
         "plain": {"ms_per_step": pms, "images_per_s": 4 / (pms * 1e-3),
                   "identical_to_batched": bool(same)},
         "speedup_images_per_s_vs_plain": pms / ms_step,
@@ -992,7 +1128,7 @@ def run_vector_workload(args, dart, torch):
                                "4 views 512^2", "components": 3, "resident_gb": gb,
                    "cell_steps_per_step": cell_steps},
         "component_cell_steps_per_s": 3 * cell_steps / (ms_step * 1e-3),
-        "images_per_s": 12 / (ms_step * 1e-3), "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
+        "images_per_s": 12 / (ms_step * 1e-3), "step_ms_p50": pct(per, 50), "step_ms_p99": pct(per, 99),
         "separate": {"ms_per_step": sms, "note": "the three components as scalar stacks, 12 "
                      "images in one batched call", "identical_to_fused": bool(same)},
         "speedup_vs_separate": sms / ms_step,
@@ -1122,6 +1258,35 @@ def pmc_summary(fetch_csv, write_csv, workload, tuning):
 
 # --------------------------------------------------------------------------- main
 
+def run_batch_workload(args, dart, torch):
+    import synth
+    views = [(th, ph, P, 0.6) for th, ph, P in synth.isotropic_views(64, 1003)]
+    name = (f"uneven batch 384^3, 32 epochs, {args.storage.upper()}, 64 isotropic views, "
+            "sides in {128,256,512,1024}")
+    if args.sides:
+        # one size class of the same 64 views (a breakdown, not the workload)
+        keep = {int(x) for x in args.sides.split(",")}
+        views = [v for v in views if v[2] in keep]
+        name += f", only the {len(views)} views of side {args.sides}"
+    storage = dart.DART_F16 if args.storage == "f16" else dart.DART_BF16
+    return run_render_workload(args, dart, torch, name, (384, 384, 384), 32, storage, views, 5.0,
+                               4, 3, 8, args.storage, check_views=8)
+
+
+def release(torch):
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def nested_object(line):
+    """A workload's line as an object inside the default line: its own metric
+    values, workload, roofline, comparisons, accuracy and CPU baseline."""
+    drop = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data")
+    return {k: v for k, v in line.items() if k not in drop}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1159,6 +1324,9 @@ def main():
                          "[,depth_sync[,cells_per_batch]]")
     ap.add_argument("--profile", action="store_true",
                     help="timed batched loop only (for rocprofv3 runs)")
+    ap.add_argument("--no-nested", dest="nested", action="store_false", default=True,
+                    help="jet workload: leave out the batched (384^3 FP16) and served objects "
+                         "that the default run adds to its line")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the traffic-table row for two rocprofv3 --pmc counter files "
                          "of a --profile run (with the same --workload/--storage/--tuning)")
@@ -1184,20 +1352,26 @@ def main():
         line = run_render_workload(
             args, dart, torch, "jet 256x256x512, 16 epochs, FP32, 4 views 512^2 (theta 10/30/60/90)",
             (256, 256, 512), 16, dart.DART_F32, views, 5.0, 4, 2, 16, "f32")
+        if args.nested and not args.profile:
+            # the batched and served forms of the same metric, in the same run
+            t0 = time.time()
+            release(torch)
+            bargs = argparse.Namespace(**vars(args))
+            bargs.workload, bargs.storage, bargs.sides = "batch", "f16", None
+            line["batch_fp16"] = nested_object(run_batch_workload(bargs, dart, torch))
+            log(f"batch object in {time.time() - t0:.0f} s")
+            t0 = time.time()
+            release(torch)
+            sargs = argparse.Namespace(**vars(args))
+            sargs.workload = "serve"
+            served = nested_object(run_serve_workload(sargs, dart, torch))
+            line["served"] = served
+            log(f"served object in {time.time() - t0:.0f} s")
+            # the metric's p50 / p99 are the served stream's latencies
+            line["p50_ms"], line["p99_ms"] = served["p50_ms"], served["p99_ms"]
+            line["latency_source"] = "served object: " + served["latency_definition"]
     elif args.workload == "batch":
-        import synth
-        views = [(th, ph, P, 0.6) for th, ph, P in synth.isotropic_views(64, 1003)]
-        name = (f"uneven batch 384^3, 32 epochs, {args.storage.upper()}, 64 isotropic views, "
-                "sides in {128,256,512,1024}")
-        if args.sides:
-            # one size class of the same 64 views (a breakdown, not the workload)
-            keep = {int(x) for x in args.sides.split(",")}
-            views = [v for v in views if v[2] in keep]
-            name += f", only the {len(views)} views of side {args.sides}"
-        storage = dart.DART_F16 if args.storage == "f16" else dart.DART_BF16
-        line = run_render_workload(
-            args, dart, torch, name, (384, 384, 384), 32, storage, views, 5.0, 4, 3, 8,
-            args.storage, check_views=8)
+        line = run_batch_workload(args, dart, torch)
     elif args.workload == "serve":
         line = run_serve_workload(args, dart, torch)
     elif args.workload == "labelled":

@@ -434,6 +434,25 @@ typedef struct {
 } dart_server_stats;
 dart_status dart_server_get_stats(dart_server *srv, dart_server_stats *st);
 
+/* Where a server's waves spend their time, summed over the waves retired so
+ * far (waves_timed of them).  Host side, per wave: planning (tile lists and
+ * descriptors), enqueueing (the descriptor upload, the render launches, the
+ * image copies and the completion callback), and the time from the
+ * completion callback to the scheduler publishing the results.  Device side,
+ * from events on the wave's stream: its whole device work (descriptor upload
+ * to accumulator readback) and its render kernels alone (kernels of waves on
+ * other streams run meanwhile, so these overlap).  stream_idle_ms sums, over
+ * the waves, how long their stream sat idle with requests waiting: from its
+ * previous wave's completion, when requests were queued at that moment, to
+ * the start of planning this one.  All times in ms. */
+typedef struct {
+    uint64_t waves_timed;
+    double plan_ms, enqueue_ms, callback_to_retire_ms;
+    double device_ms, kernel_ms;
+    double stream_idle_ms;
+} dart_server_timeline;
+dart_status dart_server_get_timeline(dart_server *srv, dart_server_timeline *tl);
+
 /* Thread-local text describing the last non-OK status on this thread. */
 const char *dart_last_error(void);
 

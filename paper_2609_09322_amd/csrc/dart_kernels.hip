@@ -73,6 +73,31 @@ __device__ __forceinline__ void decode(const typename RecT<S>::raw &r, V &j, V &
     }
 }
 
+// The velocity bits of a record, OR-ed into one word: zero exactly when the
+// three components are +0.  (A -0 component makes it non-zero; such records
+// take the general path, where they also give D = 1.)
+template <int S>
+__device__ __forceinline__ uint32_t beta_bits(const typename RecT<S>::raw &r) {
+    if constexpr (S == ST_F16 || S == ST_BF16) {
+        return (r.x & 0xffff0000u) | r.y;
+    } else if constexpr (S == ST_F32) {
+        return __float_as_uint(r.y) | __float_as_uint(r.z) | __float_as_uint(r.w);
+    } else {
+        const uint64_t b = (uint64_t)__double_as_longlong(r.y) |
+                           (uint64_t)__double_as_longlong(r.z) |
+                           (uint64_t)__double_as_longlong(r.w);
+        return (uint32_t)b | (uint32_t)(b >> 32);
+    }
+}
+
+// The rest-frame emissivity j of a record.
+template <int S>
+__device__ __forceinline__ typename RecT<S>::val record_j(const typename RecT<S>::raw &r) {
+    if constexpr (S == ST_F64 || S == ST_F32) return r.x;
+    else if constexpr (S == ST_F16) return h2f(r.x & 0xffffu);
+    else return __uint_as_float(r.x << 16);
+}
+
 // D^p of one record (Eq. 14 raised to p), and its rest-frame emissivity in j.
 template <int S>
 __device__ __forceinline__ typename RecT<S>::val boost_factor(const typename RecT<S>::raw &r,
@@ -138,18 +163,78 @@ __device__ __forceinline__ typename RecT<S>::val decode_j(typename JFieldT<S>::r
 
 // DDA state of one ray.  Per axis the plane crossings ahead of the ray form the
 // sequence base + c * ds_axis (c = crossings made so far along that axis): the
-// cell's chord is [max of the planes behind, min of the planes ahead].
+// cell's chord is [max of the planes behind, min of the planes ahead].  The
+// planes behind are not kept: the largest of them is the previous cell's exit
+// (or, for the first cell, the largest of the planes behind the start).
+// Crossing counts are kept in the ray precision (exact integers there).
 template <typename R>
 struct Ray {
     int x, y, z;
     int sx, sy, sz;      // step per axis (-1, 0, +1)
-    int c0, c1, c2;      // crossings made per axis
+    R c0, c1, c2;        // crossings made per axis
     R b0, b1, b2;        // s of the first plane ahead per axis
     R d0, d1, d2;        // plane spacing per axis (Eq. 11)
     R sa0, sa1, sa2;     // s of the plane ahead
-    R sb0, sb1, sb2;     // s of the plane behind
+    R entry;             // s where the ray enters the current cell
     R stop;              // min(exit of the grid, end of the temporal window)
+    uint32_t off;        // record offset of the current cell inside its epoch
 };
+
+// The record offset of cell (x, y, z) inside its epoch is a sum of one term per
+// axis: with bricks of 2^a x 2^b x 2^c cells (L = a + b + c bits per brick),
+//   offset = ((bz nb1 + by) nb0 + bx) 2^L + lz 2^(a+b) + ly 2^a + lx
+//          = X(x) + Y(y) + Z(z),
+//   X(x) = x + (x >> a)(2^L - 2^a)
+//   Y(y) = y 2^a + (y >> b)(nb0 2^L - 2^(a+b))
+//   Z(z) = z 2^(a+b) + (z >> c)(nb1 nb0 2^L - 2^(a+b+c))
+// (the same value cell_offset returns), so a step along one axis changes one
+// term.  The products wrap modulo 2^32 like the offsets themselves.
+//
+// A step of +-1 along x changes X by +-1, or by +-(1 + 2^L - 2^a) when it
+// crosses into the next brick, which is when the new cell's position inside
+// its brick, x mod 2^a, is 0 (stepping up) or 2^a - 1 (stepping down); y and z
+// alike.  All rays of a view step the same way along each axis, so these
+// increments and tests are uniform over a wavefront: the walk updates the
+// offset with two selects and an add, without multiplies.
+struct OffsetSteps {
+    uint32_t mask[3];    // 2^a - 1, 2^b - 1, 2^c - 1
+    uint32_t edge[3];    // the position inside the brick after a brick crossing
+    uint32_t inner[3];   // offset change of a step inside a brick
+    uint32_t cross[3];   // offset change of a step across a brick face
+};
+
+__device__ __forceinline__ OffsetSteps offset_steps(const StackDev &st, const RayView &v) {
+    OffsetSteps o;
+    const uint32_t a = st.lb[0], b = st.lb[1], c = st.lb[2], L = a + b + c;
+    const uint32_t nb0 = st.nb[0], nb1 = st.nb[1];
+    const uint32_t in_[3] = {1u, 1u << a, 1u << (a + b)};
+    const uint32_t k[3] = {(1u << L) - (1u << a), (nb0 << L) - (1u << (a + b)),
+                           ((nb1 * nb0) << L) - (1u << L)};
+    const uint32_t lb[3] = {a, b, c};
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const bool down = v.shat[q] < 0.0;
+        o.mask[q] = (1u << lb[q]) - 1u;
+        o.edge[q] = down ? o.mask[q] : 0u;
+        // (unsigned negation: a step down subtracts modulo 2^32)
+        o.inner[q] = down ? 0u - in_[q] : in_[q];
+        o.cross[q] = down ? 0u - (in_[q] + k[q]) : in_[q] + k[q];
+    }
+    return o;
+}
+__device__ __forceinline__ uint32_t off_x(const StackDev &st, int x) {
+    const uint32_t a = st.lb[0], L = st.lb[0] + st.lb[1] + st.lb[2];
+    return (uint32_t)x + ((uint32_t)x >> a) * ((1u << L) - (1u << a));
+}
+__device__ __forceinline__ uint32_t off_y(const StackDev &st, int y) {
+    const uint32_t a = st.lb[0], b = st.lb[1], L = st.lb[0] + st.lb[1] + st.lb[2];
+    return ((uint32_t)y << a) + ((uint32_t)y >> b) * (((uint32_t)st.nb[0] << L) - (1u << (a + b)));
+}
+__device__ __forceinline__ uint32_t off_z(const StackDev &st, int z) {
+    const uint32_t ab = st.lb[0] + st.lb[1], c = st.lb[2], L = ab + c;
+    return ((uint32_t)z << ab) +
+           ((uint32_t)z >> c) * ((((uint32_t)st.nb[1] * (uint32_t)st.nb[0]) << L) - (1u << L));
+}
 
 // FP64 set-up of pixel (pi, pj): slab test, clip to the window, starting cell
 // and crossing sequences.  False when no cell of the ray can contribute.
@@ -201,41 +286,49 @@ __device__ __forceinline__ bool ray_setup(const RayView &v, const StackDev &st,
     }
     r.x = idx[0]; r.y = idx[1]; r.z = idx[2];
     r.sx = stp[0]; r.sy = stp[1]; r.sz = stp[2];
-    r.c0 = r.c1 = r.c2 = 0;
+    r.c0 = r.c1 = r.c2 = (R)0;
     r.b0 = base[0]; r.b1 = base[1]; r.b2 = base[2];
     r.d0 = sp[0]; r.d1 = sp[1]; r.d2 = sp[2];
     r.sa0 = base[0]; r.sa1 = base[1]; r.sa2 = base[2];
-    r.sb0 = stp[0] ? base[0] - sp[0] : (R)-INFINITY;
-    r.sb1 = stp[1] ? base[1] - sp[1] : (R)-INFINITY;
-    r.sb2 = stp[2] ? base[2] - sp[2] : (R)-INFINITY;
+    const R sb0 = stp[0] ? base[0] - sp[0] : (R)-INFINITY;
+    const R sb1 = stp[1] ? base[1] - sp[1] : (R)-INFINITY;
+    const R sb2 = stp[2] ? base[2] - sp[2] : (R)-INFINITY;
+    r.entry = fmax(sb0, fmax(sb1, sb2));
     r.stop = (R)s_stop;
+    r.off = off_x(st, r.x) + off_y(st, r.y) + off_z(st, r.z);
     return true;
 }
 
-// Step to the neighbour across the nearest face; false when leaving the grid.
+// Step to the neighbour across the nearest face (ties: x before y before z);
+// false when leaving the grid.  exit is min(sa0, sa1, sa2), the current cell's
+// exit, which becomes the next cell's entry.  Written without branches: the
+// lanes of a wavefront step along different axes, and every axis takes the
+// same few selects instead of three divergent paths.  An axis that does not
+// step keeps its count, so its recomputed plane is the same value.
 template <typename R>
-__device__ __forceinline__ bool ray_advance(const StackDev &st, Ray<R> &r) {
+__device__ __forceinline__ bool ray_advance(const StackDev &st, const OffsetSteps &os, Ray<R> &r,
+                                            const R exit) {
     // (the crossing state of a ray that leaves the grid is not used again)
-    bool inside;
-    if (r.sa0 <= r.sa1 && r.sa0 <= r.sa2) {
-        r.x += r.sx;
-        inside = (unsigned)r.x < (unsigned)st.n[0];
-        r.c0++;
-        r.sb0 = r.sa0;
-        r.sa0 = fma((R)r.c0, r.d0, r.b0);
-    } else if (r.sa1 <= r.sa2) {
-        r.y += r.sy;
-        inside = (unsigned)r.y < (unsigned)st.n[1];
-        r.c1++;
-        r.sb1 = r.sa1;
-        r.sa1 = fma((R)r.c1, r.d1, r.b1);
-    } else {
-        r.z += r.sz;
-        inside = (unsigned)r.z < (unsigned)st.n[2];
-        r.c2++;
-        r.sb2 = r.sa2;
-        r.sa2 = fma((R)r.c2, r.d2, r.b2);
-    }
+    const bool ax = r.sa0 <= r.sa1 && r.sa0 <= r.sa2;
+    const bool ay = !ax && r.sa1 <= r.sa2;
+    const bool az = !ax && !ay;
+    r.x += ax ? r.sx : 0;
+    r.y += ay ? r.sy : 0;
+    r.z += az ? r.sz : 0;
+    r.c0 += ax ? (R)1 : (R)0;
+    r.c1 += ay ? (R)1 : (R)0;
+    r.c2 += az ? (R)1 : (R)0;
+    r.sa0 = fma(r.c0, r.d0, r.b0);
+    r.sa1 = fma(r.c1, r.d1, r.b1);
+    r.sa2 = fma(r.c2, r.d2, r.b2);
+    // (a compare and select, not fmax: no canonicalisation of the operands)
+    r.entry = exit > r.entry ? exit : r.entry;
+    const bool inside = (unsigned)r.x < (unsigned)st.n[0] && (unsigned)r.y < (unsigned)st.n[1] &&
+                        (unsigned)r.z < (unsigned)st.n[2];
+    const uint32_t dx = ((uint32_t)r.x & os.mask[0]) == os.edge[0] ? os.cross[0] : os.inner[0];
+    const uint32_t dy = ((uint32_t)r.y & os.mask[1]) == os.edge[1] ? os.cross[1] : os.inner[1];
+    const uint32_t dz = ((uint32_t)r.z & os.mask[2]) == os.edge[2] ? os.cross[2] : os.inner[2];
+    r.off += ax ? dx : (ay ? dy : dz);
     return inside;
 }
 
@@ -330,9 +423,10 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
     Bracket<R> br;
     bracket_init(v, st, lookback, br);
+    const OffsetSteps os = offset_steps(st, v);
     const uint64_t ncell = (uint64_t)st.n[0] * st.n[1] * st.n[2];
     for (int guard = st.n[0] + st.n[1] + st.n[2] + 3; guard > 0; guard--) {
-        const R entry = fmax(r.sb0, fmax(r.sb1, r.sb2));
+        const R entry = r.entry;
         const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
         if (entry >= r.stop) break;
         const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
@@ -352,7 +446,7 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
                 lin = ((uint64_t)r.z * st.n[1] + r.y) * st.n[0] + r.x;
                 stride = ncell;
             } else {
-                lin = cell_offset(st, r.x, r.y, r.z);
+                lin = r.off;
                 stride = st.epoch_stride;
             }
             const int sh = line_log2 < 0 ? 0 : line_log2;
@@ -365,7 +459,7 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
                 atomicOr(&bitmap[b >> 5], 1u << (b & 31));
             }
         }
-        if (!ray_advance(st, r)) break;
+        if (!ray_advance(st, os, r, exit)) break;
     }
 }
 
@@ -382,8 +476,32 @@ constexpr int CELLS_PER_BATCH = 4;
 // 2K records at once and consumes them after a single wait: many gathers per
 // lane in flight instead of one dependent load per step.  (K is 4 or 8 in the
 // batched kernel, CELLS_PER_BATCH in the plain one.)
-template <typename R>
-__device__ __forceinline__ R wave_min(R x) {
+// Minimum over the 64 lanes of a wavefront (every lane active): within each
+// row of 16 lanes by DPP lane permutations (swap neighbours, swap pairs, mirror
+// the half row, mirror the row), then across the four rows from one lane of
+// each.  No LDS round trips.
+__device__ __forceinline__ float dpp_min_row(float x) {
+    // DPP controls: quad_perm [1,0,3,2] = 0xb1, quad_perm [2,3,0,1] = 0x4e,
+    // row_half_mirror = 0x141, row_mirror = 0x140
+    x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
+                                                             0xb1, 0xf, 0xf, false)));
+    x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
+                                                             0x4e, 0xf, 0xf, false)));
+    x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
+                                                             0x141, 0xf, 0xf, false)));
+    x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
+                                                             0x140, 0xf, 0xf, false)));
+    return x;
+}
+__device__ __forceinline__ float wave_min(float x) {
+    x = dpp_min_row(x);
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+    return fminf(fminf(r0, r1), fminf(r2, r3));
+}
+__device__ __forceinline__ double wave_min(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
     return x;
@@ -441,6 +559,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     const int64_t second = single ? 0 : estride;
     Bracket<R> br;
     bracket_init(v, st, lookback, br, tab);
+    const OffsetSteps os = offset_steps(st, v);
     GRaw *ebase = gdata + (int64_t)br.m * estride;  // records of epoch br.m
     int ebase_m = br.m;
     A sum = 0, comp = 0;
@@ -457,7 +576,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     for (;;) {
         R front = (R)0;
         if (SYNC != 0) {
-            front = wave_min(alive ? fmax(r.sb0, fmax(r.sb1, r.sb2)) : (R)INFINITY);
+            front = wave_min(alive ? r.entry : (R)INFINITY);
             if (front == (R)INFINITY) break;  // uniform: every ray has ended
         } else if (!alive) {
             break;
@@ -470,7 +589,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
             cds[k] = (A)0;
             cw[k] = (A)0;
             if (alive) {
-                const R entry = fmax(r.sb0, fmax(r.sb1, r.sb2));
+                const R entry = r.entry;
                 const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
                 if (entry >= r.stop || budget <= 0) {
                     alive = false;
@@ -495,7 +614,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                         ebase = gdata + (int64_t)br.m * estride;
                         ebase_m = br.m;
                     }
-                    addr[k] = ebase + cell_offset(st, r.x, r.y, r.z);
+                    addr[k] = ebase + r.off;
                     cds[k] = contrib ? (A)ds : (A)0;
                     cw[k] = (A)wt;
                     count += (contrib && !cell_counted) ? 1u : 0u;
@@ -506,7 +625,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                         piece = -(R)INFINITY;
                         cell_counted = false;
                         budget--;
-                        alive = ray_advance(st, r);
+                        alive = ray_advance(st, os, r, exit);
                     }
                 } else if (!EX && (SYNC == 0 || entry - front < gap || entry <= front)) {
                     // (the rearmost ray has entry == front, so each batch
@@ -531,12 +650,12 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                         }
                         wt = (R)0;
                     }
-                    addr[k] = e0 + cell_offset(st, r.x, r.y, r.z);
+                    addr[k] = e0 + r.off;
                     cds[k] = contrib ? (A)ds : (A)0;
                     cw[k] = (A)wt;
                     count += contrib ? 1u : 0u;
                     budget--;
-                    alive = ray_advance(st, r);
+                    alive = ray_advance(st, os, r, exit);
                 }
             }
         }
@@ -564,6 +683,40 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
         // the ray or outside the window has ds = 0 (its records, validated at
         // load, are finite), and an unconditional use keeps the compiler from
         // sinking the loads back into a branch.
+        //
+        // When no record that contributes to the batch, on any lane of the
+        // wavefront, has a velocity (the bulk of a jet's volume is at rest),
+        // every Doppler factor is exactly 1: the batch is consumed without
+        // decoding velocities, with the same arithmetic on j as the general
+        // path (j * 1 = j), so the sums are bit for bit the same.
+        bool at_rest = !beaming;
+        if constexpr (!VEC) {
+            if (beaming) {
+                uint32_t moving = 0u;
+#pragma unroll
+                for (int k = 0; k < K; k++)
+                    moving |= cds[k] != (A)0 ? (beta_bits<S>(r0[k]) | beta_bits<S>(r1[k])) : 0u;
+                at_rest = !__any(moving != 0u);
+            }
+        }
+        if (!VEC && at_rest) {
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                A val = (A)record_j<S>(r0[k]);
+                const A b1 = (A)record_j<S>(r1[k]);
+                val = val + cw[k] * (b1 - val);
+                const A term = cds[k] * val;
+                if (kahan && term != (A)0) {
+                    const A yk = term - comp;
+                    const A tk = sum + yk;
+                    comp = (tk - sum) - yk;
+                    sum = tk;
+                } else {
+                    sum += term;
+                }
+            }
+            continue;
+        }
 #pragma unroll
         for (int k = 0; k < K; k++) {
             V f0 = V(1), f1 = V(1);

@@ -103,7 +103,9 @@ struct Wave {
     std::vector<Req *> reqs;
     int stream_idx = 0;
     bool done = false;
-    Clock::time_point t_done;
+    Clock::time_point t_plan;    // the scheduler starts planning the wave
+    Clock::time_point t_launch;  // its device work is enqueued
+    Clock::time_point t_done;    // the completion callback ran
     struct dart_server *srv = nullptr;
 };
 
@@ -119,6 +121,11 @@ struct dart_server {
     // (also the flux / step readback), fixed at creation and outside the budget
     std::vector<void *> desc_dev, desc_host;
     size_t desc_cap = 0;
+    // per stream: events around a wave's device work (upload .. readback) and
+    // around its render kernels, and when its previous wave completed
+    std::vector<hipEvent_t> ev_begin, ev_kbegin, ev_kend, ev_end;
+    std::vector<Clock::time_point> stream_free_at;
+    std::vector<bool> stream_waited;  // requests were queued when the stream's last wave retired
     void *dev_base = nullptr;    // device arena: images and wave descriptors
     void *host_base = nullptr;   // pinned arena: descriptor uploads, flux readback, host images
     size_t host_size = 0;
@@ -133,7 +140,12 @@ struct dart_server {
     bool stop = false;
     std::thread thr;
     dart_server_stats stats{};
+    dart_server_timeline tl{};
 };
+
+static double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
 
 static void on_wave_done(void *p) {
     Wave *w = (Wave *)p;
@@ -147,6 +159,20 @@ static void on_wave_done(void *p) {
 // Frees a finished wave's resources and publishes its results.  Caller holds mu.
 static void retire(dart_server *srv, Wave *w) {
     const size_t n = w->reqs.size();
+    {
+        // the completion callback ran after every event of the wave: all complete
+        const int k = w->stream_idx;
+        float dev_ms = 0, ker_ms = 0;
+        if (hipEventElapsedTime(&dev_ms, srv->ev_begin[k], srv->ev_end[k]) == hipSuccess &&
+            hipEventElapsedTime(&ker_ms, srv->ev_kbegin[k], srv->ev_kend[k]) == hipSuccess) {
+            srv->tl.device_ms += dev_ms;
+            srv->tl.kernel_ms += ker_ms;
+        }
+        srv->tl.callback_to_retire_ms += ms_between(w->t_done, Clock::now());
+        srv->tl.waves_timed++;
+        srv->stream_free_at[k] = w->t_done;
+        srv->stream_waited[k] = !srv->queue.empty();
+    }
     const unsigned long long *acc_h = (const unsigned long long *)srv->desc_host[w->stream_idx];
     for (size_t i = 0; i < n; i++) {
         Req *r = w->reqs[i];
@@ -224,6 +250,7 @@ static void launch_wave(dart_server *srv, std::unique_lock<std::mutex> &lk, int 
     std::unique_ptr<Wave> w(new Wave());
     w->srv = srv;
     w->stream_idx = sidx;
+    w->t_plan = Clock::now();
     // 256-B alignment of the accumulators + 64 B per request (flux, steps and
     // queue heads) on top of each request's descriptor bound
     size_t bound = 320;
@@ -273,11 +300,21 @@ static void launch_wave(dart_server *srv, std::unique_lock<std::mutex> &lk, int 
     unsigned long long *dacc = (unsigned long long *)(ddesc + acc_off);
     pack_descriptors(groups, nv, hstage);
     hipStream_t stream = srv->streams[sidx];
+    const Clock::time_point t_planned = Clock::now();
+    // the stream's idle time before this wave while requests were waiting:
+    // from its last wave's completion, if the queue held requests then
+    const double idle_ms =
+        srv->stream_waited[sidx] ? ms_between(srv->stream_free_at[sidx], wp->t_plan) : 0.0;
+    srv->stream_waited[sidx] = false;
     lk.unlock();
-    hipError_t e = hipMemcpyAsync(ddesc, hstage, desc_bytes, hipMemcpyHostToDevice, stream);
+    hipError_t e = hipEventRecord(srv->ev_begin[sidx], stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ddesc, hstage, desc_bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(srv->ev_kbegin[sidx], stream);
     if (e == hipSuccess)
         e = enqueue_plan(groups, n, dacc, (const RayView *)ddesc,
                          (const Tile *)(ddesc + nv * sizeof(RayView)), tun, srv->device, stream);
+    if (e == hipSuccess) e = hipEventRecord(srv->ev_kend[sidx], stream);
     for (int32_t i = 0; i < n && e == hipSuccess; i++) {
         Req *r = wp->reqs[i];
         if (r->host_dest)
@@ -289,11 +326,17 @@ static void launch_wave(dart_server *srv, std::unique_lock<std::mutex> &lk, int 
     // the flux and step accumulators overwrite the (already consumed) descriptor staging
     if (e == hipSuccess)
         e = hipMemcpyAsync(hstage, dacc, (size_t)n * 16, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipEventRecord(srv->ev_end[sidx], stream);
     if (e == hipSuccess) {
         for (int32_t i = 0; i < n; i++) note_use(stacks[i], stream);
         e = hipLaunchHostFunc(stream, on_wave_done, wp);
     }
+    const Clock::time_point t_enqueued = Clock::now();
     lk.lock();
+    wp->t_launch = t_enqueued;
+    srv->tl.plan_ms += ms_between(wp->t_plan, t_planned);
+    srv->tl.enqueue_ms += ms_between(t_planned, t_enqueued);
+    srv->tl.stream_idle_ms += idle_ms;
     if (e != hipSuccess) {
         // the device work may still be queued: wait for the stream before freeing
         lk.unlock();
@@ -391,6 +434,27 @@ extern "C" dart_status dart_server_create(size_t hbm_budget_bytes, int32_t max_i
         srv->desc_dev.push_back(d);
         srv->desc_host.push_back(h);
     }
+    for (int32_t k = 0; k < n_streams && e == hipSuccess; k++) {
+        hipEvent_t ev[4] = {};
+        for (int q = 0; q < 4 && e == hipSuccess; q++) e = hipEventCreate(&ev[q]);
+        srv->ev_begin.push_back(ev[0]);
+        srv->ev_kbegin.push_back(ev[1]);
+        srv->ev_kend.push_back(ev[2]);
+        srv->ev_end.push_back(ev[3]);
+    }
+    if (e != hipSuccess) {
+        for (auto *v : {&srv->ev_begin, &srv->ev_kbegin, &srv->ev_kend, &srv->ev_end})
+            for (hipEvent_t q : *v)
+                if (q) (void)hipEventDestroy(q);
+        for (void *q : srv->desc_dev) (void)hipFree(q);
+        for (void *q : srv->desc_host) (void)hipHostFree(q);
+        for (hipStream_t q : srv->streams) (void)hipStreamDestroy(q);
+        (void)hipFree(srv->dev_base);
+        (void)hipHostFree(srv->host_base);
+        return hip_fail(e, "server events");
+    }
+    srv->stream_free_at.assign(n_streams, Clock::now());
+    srv->stream_waited.assign(n_streams, false);
     dart_server *p = srv.get();
     srv->thr = std::thread(scheduler, p);
     *out = srv.release();
@@ -496,10 +560,19 @@ extern "C" dart_status dart_server_destroy(dart_server *srv) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
     }
+    for (auto *v : {&srv->ev_begin, &srv->ev_kbegin, &srv->ev_kend, &srv->ev_end})
+        for (hipEvent_t q : *v) (void)hipEventDestroy(q);
     for (void *q : srv->desc_dev) (void)hipFree(q);
     for (void *q : srv->desc_host) (void)hipHostFree(q);
     (void)hipFree(srv->dev_base);
     (void)hipHostFree(srv->host_base);
     delete srv;
+    return DART_OK;
+}
+
+extern "C" dart_status dart_server_get_timeline(dart_server *srv, dart_server_timeline *tl) {
+    if (!srv || !tl) return fail(DART_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(srv->mu);
+    *tl = srv->tl;
     return DART_OK;
 }

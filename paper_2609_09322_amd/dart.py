@@ -38,6 +38,7 @@ EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "da
            "dart_render_batch_noalloc", "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples", "dart_count_lines",
            "dart_record_bytes", "dart_bandwidth_probe", "dart_gather_probe", "dart_server_create", "dart_submit",
            "dart_poll", "dart_wait", "dart_server_destroy", "dart_server_get_stats",
+           "dart_server_get_timeline",
            "dart_last_error", "dart_version"]
 
 
@@ -66,6 +67,13 @@ class dart_tuning(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("orient", ctypes.c_int32), ("depth_sync", ctypes.c_int32),
                 ("cells_per_batch", ctypes.c_int32)]
+
+
+class dart_server_timeline(ctypes.Structure):
+    _fields_ = [("waves_timed", ctypes.c_uint64), ("plan_ms", ctypes.c_double),
+                ("enqueue_ms", ctypes.c_double), ("callback_to_retire_ms", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("stream_idle_ms", ctypes.c_double)]
 
 
 class dart_server_stats(ctypes.Structure):
@@ -137,6 +145,7 @@ def _load():
         "dart_wait": [_P, U64, _P, _P, _P],
         "dart_server_destroy": [_P],
         "dart_server_get_stats": [_P, _P],
+        "dart_server_get_timeline": [_P, _P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -537,6 +546,12 @@ def dart_server_get_stats(srv: Server) -> dart_server_stats:
     st = dart_server_stats()
     _check(_load().dart_server_get_stats(srv.handle, ctypes.byref(st)))
     return st
+
+
+def dart_server_get_timeline(srv: Server) -> dart_server_timeline:
+    tl = dart_server_timeline()
+    _check(_load().dart_server_get_timeline(srv.handle, ctypes.byref(tl)))
+    return tl
 
 
 def dart_server_destroy(srv: Server):

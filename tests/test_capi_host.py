@@ -144,6 +144,8 @@ def test_structs_match_header_layout():
     assert ctypes.sizeof(d.dart_view) == 56
     assert ctypes.sizeof(d.dart_tuning) == 28
     assert ctypes.sizeof(d.dart.dart_stream_stats) == 24
+    # dart_server_timeline: one uint64 and six doubles
+    assert ctypes.sizeof(d.dart.dart_server_timeline) == 56
 
 
 def test_product_does_not_reach_the_oracle():

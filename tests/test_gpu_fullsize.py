@@ -153,7 +153,12 @@ def test_server_mix_equals_solo(env):
     tickets = [dart.dart_submit(srv, s, v, im) for s, v, im in reqs]
     results = [dart.dart_wait(srv, t) for t in tickets]
     stats = dart.dart_server_get_stats(srv)
+    tl = dart.dart_server_get_timeline(srv)
     dart.dart_server_destroy(srv)
+    # every retired wave is timed; its render kernels are part of its device work
+    assert tl.waves_timed == stats.waves
+    assert 0.0 < tl.kernel_ms <= tl.device_ms
+    assert tl.plan_ms > 0.0 and tl.enqueue_ms > 0.0 and tl.stream_idle_ms >= 0.0
     assert stats.completed == len(reqs)
     assert stats.admission_waits > 0
     assert stats.waves > 1
