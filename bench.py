@@ -84,12 +84,12 @@ def normalise_tuning(spec):
     return spec + (",0,4" if n == 7 else ",4" if n == 8 else "")
 
 
-def measured_traffic(workload, tuning):
-    """HBM bytes per k_batch launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-    from the committed counter table, when it holds a row for this workload,
-    this kernel source and this launch shape; otherwise None and the reason."""
+def counter_row(workload, tuning):
+    """The committed counter-table row for this workload, this kernel source and
+    this launch shape: (fetch bytes, write bytes, L2 hit rate or None, source
+    text), or (None, None, None, reason) when there is none."""
     if not tuning:
-        return None, "no launch shape"
+        return None, None, None, "no launch shape"
     key, kid = tuning_key(tuning), kernel_source_id()
     rows = []
     if os.path.exists(TRAFFIC_TABLE):
@@ -100,8 +100,18 @@ def measured_traffic(workload, tuning):
                     rows.append(f)
     for f in rows:
         if f[0] == workload and f[1] == kid and f[2] == key:
-            return float(f[3]) + float(f[4]), f"counters for {workload}, tuning {key}, kernel {kid}"
-    return None, f"no counter row for {workload}, tuning {key}, kernel {kid}"
+            hit = float(f[5]) if len(f) >= 6 else None
+            return (float(f[3]), float(f[4]), hit,
+                    f"counters for {workload}, tuning {key}, kernel {kid}")
+    return None, None, None, f"no counter row for {workload}, tuning {key}, kernel {kid}"
+
+
+def measured_traffic(workload, tuning):
+    """HBM bytes per k_batch launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed counter table, when it holds a row for this workload,
+    this kernel source and this launch shape; otherwise None and the reason."""
+    fetch, write, _, src = counter_row(workload, tuning)
+    return (fetch + write if fetch is not None else None), src
 
 
 def cpu_model():
@@ -443,8 +453,15 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
     roof = None
     if achieved is not None:
         traffic, tsrc = measured_traffic(wkey, tuning)
+        l2_hit = counter_row(wkey, tuning)[2]
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tsrc,
+                "l2_hit_rate": l2_hit,
+                "l2_hit_rate_definition": "TCC_HIT / (TCC_HIT + TCC_MISS) of the render kernel, "
+                                          "from the same counter row as traffic",
+                "fetched_over_line_bytes": (traffic / line_bytes) if (traffic and line_bytes)
+                else None,
+                "line_over_compulsory_bytes": (line_bytes / compulsory) if line_bytes else None,
                 "traffic_gbs": traffic / (kernel_ms * 1e-3) / 1e9 if traffic else None,
                 "kernel": "k_batch (persistent tile-queue render)",
                 "bytes_per_launch": compulsory,
@@ -601,8 +618,17 @@ def run_serve_workload(args, dart, torch):
         reqs.append((s, dart.View(th, float(rng.uniform(0, 360)), P, P,
                                   math.sqrt(3.0) * n / P, 0.0, float(rng.uniform(0.5, 1.0)))))
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    # launch shape and bricks tuned on a sample of the requests (every stack
+    # gets the same tuning; a wave launches with its first request's stack's)
+    t0 = time.time()
+    tune_stream = torch.cuda.Stream()
+    best, best_ms = dart.dart_autotune([s for s, _ in reqs[:64]], [v for _, v in reqs[:64]],
+                                       rebrick=args.rebrick, stream=tune_stream)
+    tuning = tuning_dict(best, dart.dart_stack_get_info(stacks[0][0]))
+    tuning.update(best_ms=best_ms, tune_s=time.time() - t0, tuned_on="the first 64 requests")
+    log(f"autotune ({time.time() - t0:.1f} s): {tuning}")
     imgs = [torch.zeros((v.height, v.width), dtype=torch.float32, device="cuda") for _, v in reqs]
-    srv = dart.dart_server_create(args.budget_gb << 30, max_inflight=512, n_streams=3)
+    srv = dart.dart_server_create(args.budget_gb << 30, max_inflight=1024, n_streams=3)
 
     def timeline_delta(a, b):
         w = max(1, b.waves_timed - a.waves_timed)
@@ -702,6 +728,7 @@ def run_serve_workload(args, dart, torch):
         "waves": int(stats.waves), "max_wave_requests": int(stats.max_wave_requests),
         "timeline_poisson": timeline_delta(tl0, tl1),
         "timeline_saturation": timeline_delta(tl2, tl3),
+        "tuning": tuning,
         "served_equals_solo": {"identical": same, "checked": checked,
                                "note": "each image served in the Poisson mix against the same "
                                        "request rendered alone by the plain kernel, bit for bit"},
@@ -822,21 +849,41 @@ def run_large_workload(args, dart, torch):
     est_compulsory = (sum(samples) / 4 * n) * 8 + n * 4 * 1024 * 1024
     lines = [dart.dart_count_lines(st, v, stream) for v in views[:4]]
     est_lines = (sum(lines) / 4 * n) * 128 + n * 4 * 1024 * 1024
-    acc = None
+    acc, cpu = None, None
     if args.check:
         t1 = time.time()
-        ref = streamed_oracle_flux(torch, dims, times, seed, gamma, knots, views[:args.large_check])
+        ref, src = streamed_oracle_flux(torch, dims, times, seed, gamma, knots,
+                                        views[:args.large_check], with_source=True)
+        oracle_s = time.time() - t1
         errs = [abs(flux[k] - r[1]) / abs(r[1]) for k, r in enumerate(ref)]
-        perr = []
-        for k, r in enumerate(ref):
+        perr, serr, sflux = [], [], []
+        for k, (r, q) in enumerate(zip(ref, src)):
             g = imgs[k].cpu().numpy().astype(np.float64)
             perr.append(float(pix_err(g, r[0], float(np.abs(r[0]).max())).max()))
+            serr.append(float(pix_err(r[0], q[0], float(np.abs(q[0]).max())).max()))
+            sflux.append(abs(r[1] / q[1] - 1.0))
         acc = {"flux_rel_err": [float(e) for e in errs], "max_pixel_rel_err": perr,
-               "images_checked": len(ref), "oracle_s": time.time() - t1,
-               "tolerance": {"flux": 1e-6, "pixel": 2e-3}}
+               "cell_steps_rel_diff": [abs(int(steps[k]) - r[2]) / max(r[2], 1)
+                                       for k, r in enumerate(ref)],
+               "images_checked_whole": len(ref), "oracle_s": oracle_s,
+               "tolerance": {"flux": 1e-6, "pixel": 2e-3, "cell_steps": 1e-5},
+               "against": "FP64 snapshot-outer oracle on the stored values, every pixel",
+               "storage_error": {"max_pixel_rel_err": serr, "flux_rel_err": sflux,
+                                 "against": "the same oracle on the FP32 source fields, in the "
+                                            "same pass (reported, not graded)"}}
         log(f"oracle check: {acc}")
+        threads = min(len(os.sched_getaffinity(0)),
+                      int(os.environ.get("OMP_NUM_THREADS") or 1 << 10))
+        n_ref = sum(r[2] for r in ref)
+        cpu = {"value": 2 * n_ref / oracle_s, "unit": "cell-steps/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{len(ref)} whole images, snapshot-outer, on the stored and on the "
+                         f"source fields ({2 * n_ref} cell-steps in {oracle_s:.1f} s, the "
+                         f"device-to-host epoch readback included)",
+               "cpu_model": cpu_model()}
     achieved = est_compulsory / (float(np.mean(per)) * 1e-3) / 1e9
     traffic, tsrc = measured_traffic("large", tuning)
+    l2_hit = counter_row("large", tuning)[2]
     slabs = None
     if args.large_slabs > 1:
         torch.cuda.synchronize()
@@ -858,11 +905,12 @@ def run_large_workload(args, dart, torch):
         "speedup_images_per_s_vs_plain": pms / ms_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tsrc,
+                     "l2_hit_rate": l2_hit,
                      "bytes_per_launch": est_compulsory,
                      "bytes_definition": "compulsory records estimated from 4 counted views",
                      "line_bytes_per_launch": est_lines,
                      "line_gbs": est_lines / (float(np.mean(per)) * 1e-3) / 1e9},
-        "accuracy": acc, "tuning": tuning, "cpu_baseline": None, "slabs": slabs,
+        "accuracy": acc, "tuning": tuning, "cpu_baseline": cpu, "slabs": slabs,
     }
 
 
@@ -1252,8 +1300,11 @@ def pmc_summary(fetch_csv, write_csv, workload, tuning):
     wscale = gib_kib / pick(b, "k_copy", "WRITE_SIZE")
     fetch = pick(a, "k_batch", "FETCH_SIZE") * 1024 * fscale
     write = pick(b, "k_batch", "WRITE_SIZE") * 1024 * wscale
-    print(f"# FETCH_SIZE scale {fscale:.4f}, WRITE_SIZE scale {wscale:.4f}")
-    print(f"{workload} {kernel_source_id()} {tuning} {fetch:.0f} {write:.0f}")
+    hit = pick(b, "k_batch", "TCC_HIT_sum")
+    miss = pick(b, "k_batch", "TCC_MISS_sum")
+    print(f"# FETCH_SIZE scale {fscale:.4f}, WRITE_SIZE scale {wscale:.4f}, "
+          f"TCC_HIT {hit:.4g}, TCC_MISS {miss:.4g} (misses x 128 B = {miss * 128:.4g} B)")
+    print(f"{workload} {kernel_source_id()} {tuning} {fetch:.0f} {write:.0f} {hit / (hit + miss):.4f}")
 
 
 # --------------------------------------------------------------------------- main

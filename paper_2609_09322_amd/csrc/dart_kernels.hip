@@ -200,7 +200,7 @@ struct OffsetSteps {
     uint32_t mask[3];    // 2^a - 1, 2^b - 1, 2^c - 1
     uint32_t edge[3];    // the position inside the brick after a brick crossing
     uint32_t inner[3];   // offset change of a step inside a brick
-    uint32_t cross[3];   // offset change of a step across a brick face
+    uint32_t extra[3];   // added to it for a step across a brick face
 };
 
 __device__ __forceinline__ OffsetSteps offset_steps(const StackDev &st, const RayView &v) {
@@ -218,7 +218,7 @@ __device__ __forceinline__ OffsetSteps offset_steps(const StackDev &st, const Ra
         o.edge[q] = down ? o.mask[q] : 0u;
         // (unsigned negation: a step down subtracts modulo 2^32)
         o.inner[q] = down ? 0u - in_[q] : in_[q];
-        o.cross[q] = down ? 0u - (in_[q] + k[q]) : in_[q] + k[q];
+        o.extra[q] = down ? 0u - k[q] : k[q];
     }
     return o;
 }
@@ -325,9 +325,11 @@ __device__ __forceinline__ bool ray_advance(const StackDev &st, const OffsetStep
     r.entry = exit > r.entry ? exit : r.entry;
     const bool inside = (unsigned)r.x < (unsigned)st.n[0] && (unsigned)r.y < (unsigned)st.n[1] &&
                         (unsigned)r.z < (unsigned)st.n[2];
-    const uint32_t dx = ((uint32_t)r.x & os.mask[0]) == os.edge[0] ? os.cross[0] : os.inner[0];
-    const uint32_t dy = ((uint32_t)r.y & os.mask[1]) == os.edge[1] ? os.cross[1] : os.inner[1];
-    const uint32_t dz = ((uint32_t)r.z & os.mask[2]) == os.edge[2] ? os.cross[2] : os.inner[2];
+    // (each select takes one uniform operand and zero, so no uniform value is
+    // copied to a vector register first)
+    const uint32_t dx = os.inner[0] + (((uint32_t)r.x & os.mask[0]) == os.edge[0] ? os.extra[0] : 0u);
+    const uint32_t dy = os.inner[1] + (((uint32_t)r.y & os.mask[1]) == os.edge[1] ? os.extra[1] : 0u);
+    const uint32_t dz = os.inner[2] + (((uint32_t)r.z & os.mask[2]) == os.edge[2] ? os.extra[2] : 0u);
     r.off += ax ? dx : (ay ? dy : dz);
     return inside;
 }
@@ -391,6 +393,20 @@ __device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &s
         b.am1 = b.am;
         b.am = epoch_a<R>(v, st, tab, b.m);
         b.inv_dt = epoch_inv_dt<R>(st, tab, b.m);
+    }
+}
+
+// The same, keeping `base` (the records of epoch b.m) in step with the bracket.
+template <typename R, typename P>
+__device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &st, R mid,
+                                             Bracket<R> &b, const ldsdouble *tab, P &base,
+                                             P data, int64_t estride) {
+    while (b.m > 0 && mid > b.am) {
+        b.m--;
+        b.am1 = b.am;
+        b.am = epoch_a<R>(v, st, tab, b.m);
+        b.inv_dt = epoch_inv_dt<R>(st, tab, b.m);
+        base = data + (int64_t)b.m * estride;
     }
 }
 
@@ -574,10 +590,13 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     bool cell_counted = false;
 
     for (;;) {
-        R front = (R)0;
+        R lim = (R)0;  // depth-synchronous horizon: cells entered before it are taken
         if (SYNC != 0) {
-            front = wave_min(alive ? r.entry : (R)INFINITY);
+            const R front = wave_min(alive ? r.entry : (R)INFINITY);
             if (front == (R)INFINITY) break;  // uniform: every ray has ended
+            lim = front + gap;
+            // (at least just past the rearmost entry, whatever the rounding)
+            if (!(lim > front)) lim = nextafter(front, (R)INFINITY);
         } else if (!alive) {
             break;
         }
@@ -593,7 +612,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                 const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
                 if (entry >= r.stop || budget <= 0) {
                     alive = false;
-                } else if (EX && (SYNC == 0 || entry - front < gap || entry <= front)) {
+                } else if (EX && (SYNC == 0 || entry < lim)) {
                     // one piece [a, b] of the cell: from where the last piece
                     // ended (or the cell's entry, or the window's start) to the
                     // next epoch time or the end of cell or window
@@ -627,19 +646,15 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                         budget--;
                         alive = ray_advance(st, os, r, exit);
                     }
-                } else if (!EX && (SYNC == 0 || entry - front < gap || entry <= front)) {
-                    // (the rearmost ray has entry == front, so each batch
+                } else if (!EX && (SYNC == 0 || entry < lim)) {
+                    // (the rearmost ray has entry == front < lim, so each batch
                     // takes at least one cell or ends a ray)
                     const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
                     const bool contrib = ds > (R)0 && mid >= r_lo && mid <= r_hi;
                     R wt = (R)v.fixed_w;
                     if (lookback) {
-                        bracket_seek(v, st, mid, br, tab);
+                        bracket_seek(v, st, mid, br, tab, ebase, gdata, estride);
                         wt = (br.am - mid) * br.inv_dt;
-                    }
-                    if (br.m != ebase_m) {
-                        ebase = gdata + (int64_t)br.m * estride;
-                        ebase_m = br.m;
                     }
                     GRaw *e0 = ebase;
                     if constexpr (single) {

@@ -44,6 +44,9 @@ def test_traffic_rows_match_source_and_shape():
         assert bench.tuning_key(tuning) == r[2]
         traffic, src = bench.measured_traffic(r[0], tuning)
         assert traffic == float(r[3]) + float(r[4]), src
+        hit = bench.counter_row(r[0], tuning)[2]
+        assert hit == (float(r[5]) if len(r) >= 6 else None)
+        assert hit is None or 0.0 <= hit <= 1.0
         # another launch shape, or a size subset of the batch: no row
         other = dict(tuning, waves_per_cu=w + 4)
         assert bench.measured_traffic(r[0], other)[0] is None
