@@ -48,7 +48,10 @@ def test_traffic_rows_match_source_and_shape():
         assert hit == (float(r[5]) if len(r) >= 6 else None)
         assert hit is None or 0.0 <= hit <= 1.0
         # another launch shape, or a size subset of the batch: no row
-        other = dict(tuning, waves_per_cu=w + 4)
+        taken = {tuple(x[2].split(",")) for x in rows if x[0] == r[0] and x[1] == r[1]}
+        wo = next(c for c in range(4, 68, 4)
+                  if tuple(bench.tuning_key(dict(tuning, waves_per_cu=c)).split(",")) not in taken)
+        other = dict(tuning, waves_per_cu=wo)
         assert bench.measured_traffic(r[0], other)[0] is None
         assert bench.measured_traffic(r[0] + "-sides128", tuning)[0] is None
 
