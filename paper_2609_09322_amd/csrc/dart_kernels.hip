@@ -167,16 +167,17 @@ __device__ __forceinline__ typename RecT<S>::val decode_j(typename JFieldT<S>::r
 // planes behind are not kept: the largest of them is the previous cell's exit
 // (or, for the first cell, the largest of the planes behind the start).
 // Crossing counts are kept in the ray precision (exact integers there).
+// The cell indices are not kept either: the walk needs only the record offset
+// (updated per step, below) and the end of the ray, which includes the first
+// crossing of a grid face, evaluated with the same expression as the walk's.
 template <typename R>
 struct Ray {
-    int x, y, z;
-    int sx, sy, sz;      // step per axis (-1, 0, +1)
     R c0, c1, c2;        // crossings made per axis
     R b0, b1, b2;        // s of the first plane ahead per axis
     R d0, d1, d2;        // plane spacing per axis (Eq. 11)
     R sa0, sa1, sa2;     // s of the plane ahead
     R entry;             // s where the ray enters the current cell
-    R stop;              // min(exit of the grid, end of the temporal window)
+    R stop;              // min(first crossing of a grid face, end of the window)
     uint32_t off;        // record offset of the current cell inside its epoch
 };
 
@@ -191,14 +192,17 @@ struct Ray {
 // term.  The products wrap modulo 2^32 like the offsets themselves.
 //
 // A step of +-1 along x changes X by +-1, or by +-(1 + 2^L - 2^a) when it
-// crosses into the next brick, which is when the new cell's position inside
-// its brick, x mod 2^a, is 0 (stepping up) or 2^a - 1 (stepping down); y and z
-// alike.  All rays of a view step the same way along each axis, so these
-// increments and tests are uniform over a wavefront: the walk updates the
-// offset with two selects and an add, without multiplies.
+// crosses into the next brick, which is when the current cell is the last of
+// its brick in the direction of the step: x mod 2^a is 2^a - 1 (stepping up)
+// or 0 (stepping down); y and z alike.  The position of a cell inside its brick
+// is the low L bits of its offset, (lz << (a+b)) | (ly << a) | lx, so the test
+// reads the offset itself.  All rays of a view step the same way along each
+// axis, so these increments and tests are uniform over a wavefront: the walk
+// updates the offset with an and, a compare, two selects and an add, without
+// multiplies.
 struct OffsetSteps {
-    uint32_t mask[3];    // 2^a - 1, 2^b - 1, 2^c - 1
-    uint32_t edge[3];    // the position inside the brick after a brick crossing
+    uint32_t field[3];   // bits of lx, ly, lz in the offset
+    uint32_t last[3];    // their value in the last cell of a brick along the step
     uint32_t inner[3];   // offset change of a step inside a brick
     uint32_t extra[3];   // added to it for a step across a brick face
 };
@@ -214,11 +218,16 @@ __device__ __forceinline__ OffsetSteps offset_steps(const StackDev &st, const Ra
 #pragma unroll
     for (int q = 0; q < 3; q++) {
         const bool down = v.shat[q] < 0.0;
-        o.mask[q] = (1u << lb[q]) - 1u;
-        o.edge[q] = down ? o.mask[q] : 0u;
+        o.field[q] = ((1u << lb[q]) - 1u) * in_[q];
+        o.last[q] = down ? 0u : o.field[q];
         // (unsigned negation: a step down subtracts modulo 2^32)
         o.inner[q] = down ? 0u - in_[q] : in_[q];
-        o.extra[q] = down ? 0u - k[q] : k[q];
+        const uint32_t extra = down ? 0u - k[q] : k[q];
+        // Held in a vector register for the whole walk: the per-step select
+        // reads its condition from a scalar register pair, and an instruction
+        // takes at most one scalar operand, so a scalar `extra` would be
+        // copied to a vector register at every step.
+        asm("v_mov_b32 %0, %1" : "=v"(o.extra[q]) : "s"(extra));
     }
     return o;
 }
@@ -238,9 +247,11 @@ __device__ __forceinline__ uint32_t off_z(const StackDev &st, int z) {
 
 // FP64 set-up of pixel (pi, pj): slab test, clip to the window, starting cell
 // and crossing sequences.  False when no cell of the ray can contribute.
+// cell (if given) receives the starting cell's indices.
 template <typename R>
 __device__ __forceinline__ bool ray_setup(const RayView &v, const StackDev &st,
-                                          const double *centre, int pi, int pj, Ray<R> &r) {
+                                          const double *centre, int pi, int pj, Ray<R> &r,
+                                          int *cell = nullptr) {
     const double u = (pi + 0.5 - 0.5 * v.width) * v.ps;
     const double w = (pj + 0.5 - 0.5 * v.height) * v.ps;
     double o[3];
@@ -264,8 +275,9 @@ __device__ __forceinline__ bool ray_setup(const RayView &v, const StackDev &st,
     const double s_stop = fmin(s_out, v.s_hi);
     if (!hit || !(s_start < s_stop) || !(s_in < s_out)) return false;
     if ((v.flags & F_NO_LOOKBACK) && v.fixed_m < 0) return false;
-    int idx[3], stp[3];
+    int idx[3];
     R base[3], sp[3];
+    R stop = (R)s_stop;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const double d = v.shat[a];
@@ -274,47 +286,63 @@ __device__ __forceinline__ bool ray_setup(const RayView &v, const StackDev &st,
         k = k < 0 ? 0 : (k >= st.n[a] ? st.n[a] - 1 : k);
         idx[a] = k;
         if (d == 0.0) {
-            stp[a] = 0;
             base[a] = (R)INFINITY;
             sp[a] = (R)0;
         } else {
-            stp[a] = d > 0.0 ? 1 : -1;
             const double plane = (d > 0.0 ? (k + 1) : k) * st.cell[a];
             base[a] = (R)((plane - o[a]) * v.inv_shat[a]);
             sp[a] = (R)(st.cell[a] * fabs(v.inv_shat[a]));
+            // the grid face ahead is the plane after c_face crossings; the walk
+            // reaches it as fma(c_face, ds, base), the value taken here
+            const int c_face = d > 0.0 ? st.n[a] - 1 - k : k;
+            stop = fmin(stop, fma((R)c_face, sp[a], base[a]));
         }
     }
-    r.x = idx[0]; r.y = idx[1]; r.z = idx[2];
-    r.sx = stp[0]; r.sy = stp[1]; r.sz = stp[2];
     r.c0 = r.c1 = r.c2 = (R)0;
     r.b0 = base[0]; r.b1 = base[1]; r.b2 = base[2];
     r.d0 = sp[0]; r.d1 = sp[1]; r.d2 = sp[2];
     r.sa0 = base[0]; r.sa1 = base[1]; r.sa2 = base[2];
-    const R sb0 = stp[0] ? base[0] - sp[0] : (R)-INFINITY;
-    const R sb1 = stp[1] ? base[1] - sp[1] : (R)-INFINITY;
-    const R sb2 = stp[2] ? base[2] - sp[2] : (R)-INFINITY;
+    const R sb0 = v.shat[0] != 0.0 ? base[0] - sp[0] : (R)-INFINITY;
+    const R sb1 = v.shat[1] != 0.0 ? base[1] - sp[1] : (R)-INFINITY;
+    const R sb2 = v.shat[2] != 0.0 ? base[2] - sp[2] : (R)-INFINITY;
     r.entry = fmax(sb0, fmax(sb1, sb2));
-    r.stop = (R)s_stop;
-    r.off = off_x(st, r.x) + off_y(st, r.y) + off_z(st, r.z);
-    return true;
+    r.stop = stop;
+    r.off = off_x(st, idx[0]) + off_y(st, idx[1]) + off_z(st, idx[2]);
+    if (cell) {
+        cell[0] = idx[0]; cell[1] = idx[1]; cell[2] = idx[2];
+    }
+    return r.entry < r.stop;
 }
 
-// Step to the neighbour across the nearest face (ties: x before y before z);
-// false when leaving the grid.  exit is min(sa0, sa1, sa2), the current cell's
-// exit, which becomes the next cell's entry.  Written without branches: the
-// lanes of a wavefront step along different axes, and every axis takes the
-// same few selects instead of three divergent paths.  An axis that does not
-// step keeps its count, so its recomputed plane is the same value.
+// The axis of the next crossing (ties: x before y before z); exit is
+// min(sa0, sa1, sa2), the current cell's exit.
 template <typename R>
-__device__ __forceinline__ bool ray_advance(const StackDev &st, const OffsetSteps &os, Ray<R> &r,
-                                            const R exit) {
-    // (the crossing state of a ray that leaves the grid is not used again)
-    const bool ax = r.sa0 <= r.sa1 && r.sa0 <= r.sa2;
-    const bool ay = !ax && r.sa1 <= r.sa2;
-    const bool az = !ax && !ay;
-    r.x += ax ? r.sx : 0;
-    r.y += ay ? r.sy : 0;
-    r.z += az ? r.sz : 0;
+__device__ __forceinline__ void step_axis(const Ray<R> &r, const R exit, bool &ax, bool &ay,
+                                          bool &az) {
+    ax = r.sa0 == exit;
+    ay = !ax && r.sa1 == exit;
+    az = !ax && !ay;
+}
+
+// Step to the neighbour across the nearest face; false when the ray has ended
+// (it crossed a grid face or the end of the window).  exit becomes the next
+// cell's entry.  Written without branches: the lanes of a wavefront step along
+// different axes, and every axis takes the same few selects instead of three
+// divergent paths.  An axis that does not step keeps its count, so its
+// recomputed plane is the same value.  Since the crossings are taken in order
+// of s, every cell entered before the crossing that ends the ray has entry
+// below stop; a cell entered on a tie with it has no chord.
+template <typename R>
+__device__ __forceinline__ bool ray_advance(const OffsetSteps &os, Ray<R> &r, const R exit) {
+    bool ax, ay, az;
+    step_axis(r, exit, ax, ay, az);
+    // brick face ahead along each axis, from the current cell's offset (each
+    // select takes one uniform operand and zero, so no uniform value is copied
+    // to a vector register first)
+    const uint32_t dx = os.inner[0] + ((r.off & os.field[0]) == os.last[0] ? os.extra[0] : 0u);
+    const uint32_t dy = os.inner[1] + ((r.off & os.field[1]) == os.last[1] ? os.extra[1] : 0u);
+    const uint32_t dz = os.inner[2] + ((r.off & os.field[2]) == os.last[2] ? os.extra[2] : 0u);
+    r.off += ax ? dx : (ay ? dy : dz);
     r.c0 += ax ? (R)1 : (R)0;
     r.c1 += ay ? (R)1 : (R)0;
     r.c2 += az ? (R)1 : (R)0;
@@ -323,15 +351,7 @@ __device__ __forceinline__ bool ray_advance(const StackDev &st, const OffsetStep
     r.sa2 = fma(r.c2, r.d2, r.b2);
     // (a compare and select, not fmax: no canonicalisation of the operands)
     r.entry = exit > r.entry ? exit : r.entry;
-    const bool inside = (unsigned)r.x < (unsigned)st.n[0] && (unsigned)r.y < (unsigned)st.n[1] &&
-                        (unsigned)r.z < (unsigned)st.n[2];
-    // (each select takes one uniform operand and zero, so no uniform value is
-    // copied to a vector register first)
-    const uint32_t dx = os.inner[0] + (((uint32_t)r.x & os.mask[0]) == os.edge[0] ? os.extra[0] : 0u);
-    const uint32_t dy = os.inner[1] + (((uint32_t)r.y & os.mask[1]) == os.edge[1] ? os.extra[1] : 0u);
-    const uint32_t dz = os.inner[2] + (((uint32_t)r.z & os.mask[2]) == os.edge[2] ? os.extra[2] : 0u);
-    r.off += ax ? dx : (ay ? dy : dz);
-    return inside;
+    return r.entry < r.stop;
 }
 
 // Epoch bracket in s: a_m = t_obs - t_m decreases with m; the bracket m holds
@@ -433,7 +453,10 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
                                          int line_log2) {
     Ray<R> r;
     const StackDev &st = v.st;
-    if (!ray_setup(v, st, v.centre, pi, pj, r)) return;
+    int cell[3];
+    if (!ray_setup(v, st, v.centre, pi, pj, r, cell)) return;
+    const int step[3] = {v.shat[0] > 0.0 ? 1 : -1, v.shat[1] > 0.0 ? 1 : -1,
+                         v.shat[2] > 0.0 ? 1 : -1};
     const bool lookback = !(v.flags & F_NO_LOOKBACK);
     const bool single = (v.flags & F_NEAREST) || st.n_epochs == 1;
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
@@ -459,7 +482,7 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
             }
             uint64_t lin, stride;
             if (line_log2 < 0) {
-                lin = ((uint64_t)r.z * st.n[1] + r.y) * st.n[0] + r.x;
+                lin = ((uint64_t)cell[2] * st.n[1] + cell[1]) * st.n[0] + cell[0];
                 stride = ncell;
             } else {
                 lin = r.off;
@@ -475,7 +498,12 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
                 atomicOr(&bitmap[b >> 5], 1u << (b & 31));
             }
         }
-        if (!ray_advance(st, os, r, exit)) break;
+        bool ax, ay, az;
+        step_axis(r, exit, ax, ay, az);
+        cell[0] += ax ? step[0] : 0;
+        cell[1] += ay ? step[1] : 0;
+        cell[2] += az ? step[2] : 0;
+        if (!ray_advance(os, r, exit)) break;
     }
 }
 
@@ -484,29 +512,25 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
 // comes with K = 4 and K = 8 (a tuning choice); the plain kernel uses 4.
 constexpr int CELLS_PER_BATCH = 4;
 
-// Marches pixel (pi, pj) of view v and returns its intensity (FP64 for the
-// caller's reductions); adds the counted cell-steps to nsteps.
-//
-// The walk does not depend on the data it reads, so each lane first walks a
-// batch of K cells (chord, epoch weight, record addresses), then requests the
-// 2K records at once and consumes them after a single wait: many gathers per
-// lane in flight instead of one dependent load per step.  (K is 4 or 8 in the
-// batched kernel, CELLS_PER_BATCH in the plain one.)
 // Minimum over the 64 lanes of a wavefront (every lane active): within each
 // row of 16 lanes by DPP lane permutations (swap neighbours, swap pairs, mirror
 // the half row, mirror the row), then across the four rows from one lane of
-// each.  No LDS round trips.
+// each.  No LDS round trips.  The operands are entries of the walk (never NaN),
+// so a compare and select stands in for fminf, which would first quiet its
+// operands; every source lane of these permutations lies in its own row and is
+// active, so the DPP moves need no old value.
+__device__ __forceinline__ float min_sel(float a, float b) { return b < a ? b : a; }
 __device__ __forceinline__ float dpp_min_row(float x) {
     // DPP controls: quad_perm [1,0,3,2] = 0xb1, quad_perm [2,3,0,1] = 0x4e,
     // row_half_mirror = 0x141, row_mirror = 0x140
-    x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
-                                                             0xb1, 0xf, 0xf, false)));
-    x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
-                                                             0x4e, 0xf, 0xf, false)));
-    x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
-                                                             0x141, 0xf, 0xf, false)));
-    x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
-                                                             0x140, 0xf, 0xf, false)));
+    x = min_sel(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf,
+                                                              0xf, true)));
+    x = min_sel(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4e, 0xf,
+                                                              0xf, true)));
+    x = min_sel(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xf,
+                                                              0xf, true)));
+    x = min_sel(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xf,
+                                                              0xf, true)));
     return x;
 }
 __device__ __forceinline__ float wave_min(float x) {
@@ -515,12 +539,21 @@ __device__ __forceinline__ float wave_min(float x) {
     const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
     const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
     const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+    // (on scalar operands fminf is cheaper: one min of three)
     return fminf(fminf(r0, r1), fminf(r2, r3));
 }
 __device__ __forceinline__ double wave_min(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
     return x;
+}
+
+// lo <= s <= hi (lo <= hi, no NaN): in FP32 one median-of-three and a compare.
+__device__ __forceinline__ bool in_window(float s, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(s, lo, hi) == s;
+}
+__device__ __forceinline__ bool in_window(double s, double lo, double hi) {
+    return s >= lo && s <= hi;
 }
 
 // Marching modes (SYNC):
@@ -542,6 +575,15 @@ __device__ __forceinline__ double wave_min(double x) {
 // returned in ext[0..2].
 // SINGLE: one epoch per cell (nearest-epoch mode, or a one-epoch stack), a
 // property of the view and stack, so each lane's walk has no per-cell test.
+//
+// Marches pixel (pi, pj) of view v and returns its intensity (FP64 for the
+// caller's reductions); adds the counted cell-steps to nsteps.
+//
+// The walk does not depend on the data it reads, so each lane first walks a
+// batch of K cells (chord, epoch weight, record addresses), then requests the
+// 2K records at once and consumes them after a single wait: many gathers per
+// lane in flight instead of one dependent load per step.  (K is 4 or 8 in the
+// batched kernel, CELLS_PER_BATCH in the plain one.)
 template <int S, typename R, int SYNC, bool EX, int K, bool VEC, bool SINGLE>
 __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &st,
                                              const double *centre, int pi, int pj, bool in_image,
@@ -584,12 +626,17 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     for (int c = 0; c < NX; c++) xsum[c] = xcomp[c] = 0;
     const int nx = VEC ? v.n_chan - 1 : 0;
     uint32_t count = 0;
-    // a ray crosses at most n0 + n1 + n2 - 2 cells
-    int budget = st.n[0] + st.n[1] + st.n[2] + 3;
+    // A ray crosses at most n0 + n1 + n2 - 2 cells (in EX, each cell is cut at
+    // most once more per epoch time and window end).  Every batch takes a cell
+    // or piece of each live ray (SYNC == 0), or at least of the wavefront's
+    // rearmost ray, so the batches are bounded; the bound only guards against
+    // a walk that does not advance.
+    int guard = (st.n[0] + st.n[1] + st.n[2] + (EX ? M + 3 : 1)) * (SYNC != 0 ? 64 : 1);
     R piece = -(R)INFINITY;  // EX: start of the part of the current cell not yet taken
     bool cell_counted = false;
 
     for (;;) {
+        if (--guard < 0) break;
         R lim = (R)0;  // depth-synchronous horizon: cells entered before it are taken
         if (SYNC != 0) {
             const R front = wave_min(alive ? r.entry : (R)INFINITY);
@@ -610,9 +657,9 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
             if (alive) {
                 const R entry = r.entry;
                 const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
-                if (entry >= r.stop || budget <= 0) {
-                    alive = false;
-                } else if (EX && (SYNC == 0 || entry < lim)) {
+                // (a live ray's cell has entry < stop: checked at set-up and
+                // by every step)
+                if (EX && (SYNC == 0 || entry < lim)) {
                     // one piece [a, b] of the cell: from where the last piece
                     // ended (or the cell's entry, or the window's start) to the
                     // next epoch time or the end of cell or window
@@ -643,14 +690,13 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                     } else {
                         piece = -(R)INFINITY;
                         cell_counted = false;
-                        budget--;
-                        alive = ray_advance(st, os, r, exit);
+                        alive = ray_advance(os, r, exit);
                     }
                 } else if (!EX && (SYNC == 0 || entry < lim)) {
                     // (the rearmost ray has entry == front < lim, so each batch
                     // takes at least one cell or ends a ray)
                     const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
-                    const bool contrib = ds > (R)0 && mid >= r_lo && mid <= r_hi;
+                    const bool contrib = ds > (R)0 && in_window(mid, r_lo, r_hi);
                     R wt = (R)v.fixed_w;
                     if (lookback) {
                         bracket_seek(v, st, mid, br, tab, ebase, gdata, estride);
@@ -669,8 +715,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                     cds[k] = contrib ? (A)ds : (A)0;
                     cw[k] = (A)wt;
                     count += contrib ? 1u : 0u;
-                    budget--;
-                    alive = ray_advance(st, os, r, exit);
+                    alive = ray_advance(os, r, exit);
                 }
             }
         }
