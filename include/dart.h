@@ -83,6 +83,9 @@ typedef enum { DART_F64 = 0, DART_F32 = 1, DART_F16 = 2, DART_BF16 = 3 } dart_dt
                                    A cell still counts as one cell-step.  Lookback with linear
                                    interpolation only (not with DART_NEAREST_EPOCH); not
                                    accepted by dart_streamer_render */
+#define DART_RECORDS_ONLY 0x200u /* view: read the whole record of every cell instead of the
+                                   stack's emissivity plane (see dart_stack_get_info); the
+                                   image is the same bit for bit: for comparisons */
 #define DART_ACCUMULATE 0x80u   /* view: add the render to the values already in the image
                                    instead of overwriting them, so partial renders of
                                    sub-domains sum into one buffer (Sec. 4, Fig. 5; Sec. 6.2).
@@ -131,12 +134,24 @@ dart_status dart_stack_set_epochs(dart_stack *s, int32_t m0, int32_t count, dart
  * reads it is still running on the device. */
 dart_status dart_free_epochs(dart_stack *s);
 
+/* Emissivity plane.  A plain stack with FP32, FP16 or BF16 records also keeps
+ * its emissivity alone, one value per record at the record's own index (a
+ * quarter of the record bytes), packed on the device by the first render
+ * after its records change (not inside a stream capture, and by
+ * dart_render_batch_noalloc only into a plane already allocated).  The value's
+ * sign bit marks records that must be read whole: any velocity bit set, or a
+ * negative (or -0) emissivity.  A render reads the plane, and the whole records
+ * only of the batches of cells where a contributing record carries the mark; a
+ * jet's volume at rest is then read at a quarter of the bytes.  Images, flux
+ * and cell-steps are bit for bit those of whole-record reads
+ * (DART_RECORDS_ONLY).  Without room for the plane (hipMalloc fails) renders
+ * read whole records.  FP64, labelled, vector and streamed stacks have none. */
 typedef struct {
     int32_t dims[3];
     int32_t n_epochs;
     dart_dtype storage;
     int32_t brick[3];      /* resident brick shape (cells) */
-    uint64_t device_bytes; /* resident bytes */
+    uint64_t device_bytes; /* resident bytes: records, and the emissivity plane once packed */
 } dart_stack_info;
 dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info *info);
 
@@ -376,6 +391,17 @@ dart_status dart_count_samples(const dart_stack *s, const dart_view *v, uint64_t
  * instrumentation, as above. */
 dart_status dart_count_lines(const dart_stack *s, const dart_view *v, uint64_t *lines_out,
                              void *hip_stream);
+
+/* The same counts as renders read the stack: with the emissivity plane (packed
+ * first if it is missing or stale), each sample of positive weight costs one
+ * plane value (a quarter of a record) and, when its record carries the
+ * read-whole mark, the record as well; without it (DART_RECORDS_ONLY, or no
+ * plane) a record.  compulsory_out: those bytes; line_bytes_out: the distinct
+ * 128-byte lines of the plane and of the records that hold them, times 128.
+ * The image bytes are not included.  Either output may be NULL.  Untimed
+ * instrumentation, as above. */
+dart_status dart_count_bytes(const dart_stack *s, const dart_view *v, uint64_t *compulsory_out,
+                             uint64_t *line_bytes_out, void *hip_stream);
 
 /* Bytes of one resident record (j, beta_x, beta_y, beta_z) of a stack. */
 dart_status dart_record_bytes(const dart_stack *s, uint32_t *bytes_out);

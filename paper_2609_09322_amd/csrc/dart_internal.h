@@ -23,6 +23,11 @@ enum : uint32_t {
 // 2^lb[0] x 2^lb[1] x 2^lb[2] cells (x fastest inside a brick, bricks x-fastest).
 struct StackDev {
     const void *data;       // resident records
+    // Emissivity plane: the j field of every record packed alone, at the
+    // record's own index, in the storage type (FP32, or the 16-bit bits); its
+    // sign bit is set when the record must be read whole (velocity bits not
+    // all zero, or j itself negative or -0).  Null: read whole records.
+    const void *jplane;
     const double *times;    // [M] epoch times (device)
     const double *inv_dt;   // [M] 1 / (t_{m+1} - t_m), 0 for the last epoch (device)
     int64_t epoch_stride;   // records from one epoch to the next (padded to whole bricks;
@@ -98,11 +103,17 @@ hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *
                         hipStream_t s);
 // Kernel variant bits: 1 depth-synchronous wavefronts, 2 the launch's views are
 // labelled stacks (block loop), 4 exact temporal integration, 8 eight cells per
-// batch (else four), 16 vector stacks (only alone: no other bit but 8).
-enum : int { KV_SYNC = 1, KV_LABELLED = 2, KV_EXACT = 4, KV_K8 = 8, KV_VEC = 16 };
+// batch (else four), 16 vector stacks (only alone: no other bit but 8), 32 the
+// views' stacks have an emissivity plane (not with 2 or 16).
+enum : int { KV_SYNC = 1, KV_LABELLED = 2, KV_EXACT = 4, KV_K8 = 8, KV_VEC = 16, KV_JP = 32 };
 hipError_t launch_batch(int store, bool f64_dda, int variant, const BatchLaunch &bl,
                         int grid_blocks, hipStream_t s);
-hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s);
+// Marks the samples of positive weight of a render of v (moving_only: only
+// those whose record must be read whole, see StackDev::jplane) in a bitmap of
+// records (line_log2 < 0) or of lines of 2^line_log2 elements of the record
+// index space.
+hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, bool moving_only,
+                       hipStream_t s);
 hipError_t launch_popcount(const uint32_t *bitmap, uint64_t words, unsigned long long *out,
                            hipStream_t s);
 hipError_t launch_convert(int src_f64, int store, const void *j, const void *beta, int32_t m0,
@@ -115,6 +126,9 @@ hipError_t launch_rebrick(int store, const StackDev &from, const StackDev &to, v
 hipError_t launch_read_epoch(const StackDev &st, int32_t m, void *j, void *beta, hipStream_t s);
 // Emissivity fields of n resident records into a packed array (vector stacks).
 hipError_t launch_pack_j(int store, const void *records, void *out, uint64_t n, hipStream_t s);
+// The emissivity plane of n records (StackDev::jplane); FP32 and 16-bit storage.
+hipError_t launch_pack_jplane(int store, const void *records, void *out, uint64_t n,
+                              hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,
                            hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);

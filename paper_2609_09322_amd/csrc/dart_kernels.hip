@@ -159,6 +159,28 @@ __device__ __forceinline__ typename RecT<S>::val decode_j(typename JFieldT<S>::r
     else return __uint_as_float((uint32_t)w << 16);
 }
 
+// Emissivity plane (StackDev::jplane): one element per record, j alone in the
+// storage type, with its sign bit standing for "read the whole record": set
+// when the velocity bits are not all zero or j itself has its sign bit set
+// (negative, or -0).  An element without the mark is the record's j, exactly.
+template <int S>
+__device__ __forceinline__ uint32_t jplane_mark(typename JFieldT<S>::raw w) {
+    if constexpr (S == ST_F32) return __float_as_uint(w) >> 31;
+    else return (uint32_t)w >> 15;
+}
+template <int S>
+__device__ __forceinline__ typename JFieldT<S>::raw jplane_element(const typename RecT<S>::raw &r) {
+    if constexpr (S == ST_F32) {
+        const uint32_t jb = __float_as_uint(r.x);
+        const uint32_t mark = (beta_bits<S>(r) != 0u || (jb >> 31)) ? 1u : 0u;
+        return __uint_as_float((jb & 0x7fffffffu) | (mark << 31));
+    } else {
+        const uint32_t jb = r.x & 0xffffu;
+        const uint32_t mark = (beta_bits<S>(r) != 0u || (jb >> 15)) ? 1u : 0u;
+        return (typename JFieldT<S>::raw)((jb & 0x7fffu) | (mark << 15));
+    }
+}
+
 // ------------------------------------------------------------------ one ray
 
 // DDA state of one ray.  Per axis the plane crossings ahead of the ray form the
@@ -445,12 +467,15 @@ __device__ __forceinline__ void bracket_seek_from(const RayView &v, const StackD
 
 // Sample marking for the compulsory-bytes count: sets the (epoch, cell) bits
 // of positive weight in `bitmap` ([M][nz][ny][nx] bits).
-// line_log2 >= 0 marks instead the 128-byte lines of the resident layout that
-// hold those records (2^line_log2 records per line): bit (record index in the
-// stack) >> line_log2.
-template <typename R>
+// line_log2 >= 0 marks instead the lines of 2^line_log2 elements of the record
+// index space that hold those samples (128-byte lines of the records, or of the
+// emissivity plane): bit (record index in the stack) >> line_log2.
+// moving_only: only the samples whose record carries the emissivity plane's
+// read-whole mark.
+template <int S, typename R>
 __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint32_t *bitmap,
-                                         int line_log2) {
+                                         int line_log2, bool moving_only) {
+    using Raw = typename RecT<S>::raw;
     Ray<R> r;
     const StackDev &st = v.st;
     int cell[3];
@@ -489,11 +514,20 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
                 stride = st.epoch_stride;
             }
             const int sh = line_log2 < 0 ? 0 : line_log2;
-            if (single || wt < (R)1) {
+            // (the whole-record mark of the sample of epoch m)
+            auto whole = [&](int m) {
+                const Raw *rec = (const Raw *)st.data + ((int64_t)m * st.epoch_stride + r.off);
+                if constexpr (S == ST_F64) {
+                    return beta_bits<S>(*rec) != 0u || signbit(rec->x);
+                } else {
+                    return jplane_mark<S>(jplane_element<S>(*rec)) != 0u;
+                }
+            };
+            if ((single || wt < (R)1) && (!moving_only || whole(m0))) {
                 const uint64_t b = ((uint64_t)m0 * stride + lin) >> sh;
                 atomicOr(&bitmap[b >> 5], 1u << (b & 31));
             }
-            if (!single && wt > (R)0) {
+            if (!single && wt > (R)0 && (!moving_only || whole(m0 + 1))) {
                 const uint64_t b = ((uint64_t)(m0 + 1) * stride + lin) >> sh;
                 atomicOr(&bitmap[b >> 5], 1u << (b & 31));
             }
@@ -584,7 +618,7 @@ __device__ __forceinline__ bool in_window(double s, double lo, double hi) {
 // 2K records at once and consumes them after a single wait: many gathers per
 // lane in flight instead of one dependent load per step.  (K is 4 or 8 in the
 // batched kernel, CELLS_PER_BATCH in the plain one.)
-template <int S, typename R, int SYNC, bool EX, int K, bool VEC, bool SINGLE>
+template <int S, typename R, int SYNC, bool EX, int K, bool VEC, bool SINGLE, bool JP>
 __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &st,
                                              const double *centre, int pi, int pj, bool in_image,
                                              const ldsdouble *tab, uint32_t &nsteps,
@@ -595,6 +629,11 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     using GRaw = const Raw __attribute__((address_space(1)));
     using JF = typename JFieldT<S>::raw;
     using GJ = const JF __attribute__((address_space(1)));
+    static_assert(!(JP && (VEC || S == ST_F64)), "no emissivity plane for these stacks");
+    // The walk addresses elements of the emissivity plane (JP) or records:
+    // both have the record index space, so one offset serves either.
+    using E = typename std::conditional<JP, JF, Raw>::type;
+    using GE = const E __attribute__((address_space(1)));
     constexpr int NX = VEC ? 3 : 1;  // extra component slots
     if constexpr (VEC) {
 #pragma unroll
@@ -611,6 +650,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
     const R gap = (R)v.sync_gap;
     GRaw *gdata = (GRaw *)st.data;
+    GE *wdata = JP ? (GE *)st.jplane : (GE *)st.data;
     const int64_t estride = st.epoch_stride;
     // offset of the second record: the next epoch, or the same record when
     // only one epoch is used
@@ -618,7 +658,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     Bracket<R> br;
     bracket_init(v, st, lookback, br, tab);
     const OffsetSteps os = offset_steps(st, v);
-    GRaw *ebase = gdata + (int64_t)br.m * estride;  // records of epoch br.m
+    GE *ebase = wdata + (int64_t)br.m * estride;  // elements of epoch br.m
     int ebase_m = br.m;
     A sum = 0, comp = 0;
     A xsum[NX], xcomp[NX];
@@ -647,11 +687,11 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
         } else if (!alive) {
             break;
         }
-        GRaw *addr[K];
+        GE *addr[K];
         A cds[K], cw[K];  // chord and weight, already in the accumulation type
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            addr[k] = gdata;  // a valid address for cells not taken in this batch
+            addr[k] = wdata;  // a valid address for cells not taken in this batch
             cds[k] = (A)0;
             cw[k] = (A)0;
             if (alive) {
@@ -677,7 +717,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                     const bool contrib = ds > (R)0;
                     const R wt = (br.am - mid) * br.inv_dt;
                     if (br.m != ebase_m) {
-                        ebase = gdata + (int64_t)br.m * estride;
+                        ebase = wdata + (int64_t)br.m * estride;
                         ebase_m = br.m;
                     }
                     addr[k] = ebase + r.off;
@@ -699,10 +739,10 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                     const bool contrib = ds > (R)0 && in_window(mid, r_lo, r_hi);
                     R wt = (R)v.fixed_w;
                     if (lookback) {
-                        bracket_seek(v, st, mid, br, tab, ebase, gdata, estride);
+                        bracket_seek(v, st, mid, br, tab, ebase, wdata, estride);
                         wt = (br.am - mid) * br.inv_dt;
                     }
-                    GRaw *e0 = ebase;
+                    GE *e0 = ebase;
                     if constexpr (single) {
                         if (M >= 2) {
                             const bool later =
@@ -721,20 +761,63 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
         }
         Raw r0[K], r1[K];
         JF j0[K][NX], j1[K][NX];
+        if constexpr (JP) {
+            // Emissivity elements first.  When no record that contributes to
+            // the batch, on any lane, carries the read-whole mark, every one of
+            // them is at rest with j >= 0 and the element is its j: the batch
+            // is consumed from the elements with the arithmetic of the at-rest
+            // path below, and its sums are bit for bit those of the records.
+            JF q0[K], q1[K];
 #pragma unroll
-        for (int k = 0; k < K; k++) {
-            r0[k] = load_grec<S>(addr[k]);
-            r1[k] = load_grec<S>(addr[k] + second);
-            if constexpr (VEC) {
-                // the same record index in the other components
-                const int64_t ri = addr[k] - gdata;
+            for (int k = 0; k < K; k++) {
+                q0[k] = addr[k][0];
+                q1[k] = addr[k][second];
+            }
+            uint32_t whole = 0u;
 #pragma unroll
-                for (int c = 0; c < NX; c++) {
-                    j0[k][c] = j1[k][c] = (JF)0;
-                    if (c < nx) {
-                        GJ *cd = (GJ *)v.chan_data[c];
-                        j0[k][c] = cd[ri];
-                        j1[k][c] = cd[ri + second];
+            for (int k = 0; k < K; k++)
+                whole |= cds[k] != (A)0 ? (jplane_mark<S>(q0[k]) | jplane_mark<S>(q1[k])) : 0u;
+            if (!__any(whole != 0u)) {
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    A val = (A)decode_j<S>(q0[k]);
+                    const A b1 = (A)decode_j<S>(q1[k]);
+                    val = val + cw[k] * (b1 - val);
+                    const A term = cds[k] * val;
+                    if (kahan && term != (A)0) {
+                        const A yk = term - comp;
+                        const A tk = sum + yk;
+                        comp = (tk - sum) - yk;
+                        sum = tk;
+                    } else {
+                        sum += term;
+                    }
+                }
+                continue;
+            }
+            // the same cells' whole records, then the record path
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                GRaw *ra = gdata + (addr[k] - wdata);
+                r0[k] = load_grec<S>(ra);
+                r1[k] = load_grec<S>(ra + second);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                r0[k] = load_grec<S>(addr[k]);
+                r1[k] = load_grec<S>(addr[k] + second);
+                if constexpr (VEC) {
+                    // the same record index in the other components
+                    const int64_t ri = addr[k] - wdata;
+#pragma unroll
+                    for (int c = 0; c < NX; c++) {
+                        j0[k][c] = j1[k][c] = (JF)0;
+                        if (c < nx) {
+                            GJ *cd = (GJ *)v.chan_data[c];
+                            j0[k][c] = cd[ri];
+                            j1[k][c] = cd[ri + second];
+                        }
                     }
                 }
             }
@@ -832,17 +915,17 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     return (double)sum - (double)comp;
 }
 
-template <int S, typename R, int SYNC, bool EX, int K, bool VEC = false>
+template <int S, typename R, int SYNC, bool EX, int K, bool VEC = false, bool JP = false>
 __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                                         const double *centre, int pi, int pj, bool in_image,
                                         const ldsdouble *tab, uint32_t &nsteps,
                                         double *ext = nullptr) {
     // uniform over the launch's view (flags, epoch count): a scalar branch
     if ((v.flags & F_NEAREST) || st.n_epochs == 1)
-        return march_walk<S, R, SYNC, EX, K, VEC, true>(v, st, centre, pi, pj, in_image, tab,
-                                                         nsteps, ext);
-    return march_walk<S, R, SYNC, EX, K, VEC, false>(v, st, centre, pi, pj, in_image, tab, nsteps,
-                                                      ext);
+        return march_walk<S, R, SYNC, EX, K, VEC, true, JP>(v, st, centre, pi, pj, in_image, tab,
+                                                             nsteps, ext);
+    return march_walk<S, R, SYNC, EX, K, VEC, false, JP>(v, st, centre, pi, pj, in_image, tab,
+                                                          nsteps, ext);
 }
 
 // Intensity of pixel (pi, pj): one march through the stack, or, for a labelled
@@ -850,7 +933,8 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
 // (emission adds along the ray; sub-domains do not overlap).  The block loop
 // is uniform over the wavefront, as the depth-synchronous mode needs.
 // Vector stacks (VEC, never with LAB) also return components 1.. in ext.
-template <int S, typename R, int SYNC, bool LAB, bool EX, int K, bool VEC = false>
+template <int S, typename R, int SYNC, bool LAB, bool EX, int K, bool VEC = false,
+          bool JP = false>
 __device__ __forceinline__ double pixel_value(const RayView &v, int pi, int pj, bool in_image,
                                               const ldsdouble *tab, uint32_t &nsteps,
                                               double *ext = nullptr) {
@@ -858,9 +942,10 @@ __device__ __forceinline__ double pixel_value(const RayView &v, int pi, int pj, 
     // otherwise raise the register count, and lower the occupancy, of every
     // plain render)
     static_assert(!(LAB && VEC), "vector stacks are not labelled");
+    static_assert(!(LAB && JP), "labelled stacks read whole records");
     if constexpr (!LAB) {
-        return march<S, R, SYNC, EX, K, VEC>(v, v.st, v.centre, pi, pj, in_image, tab, nsteps,
-                                             ext);
+        return march<S, R, SYNC, EX, K, VEC, JP>(v, v.st, v.centre, pi, pj, in_image, tab, nsteps,
+                                                 ext);
     } else {
         double acc = 0.0;
         for (int b = 0; b < v.n_blocks; b++)
@@ -901,7 +986,7 @@ __device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, do
 // ------------------------------------------------------------------ kernels
 
 // Plain kernel: one thread per pixel in row order, one launch per image.
-template <int S, typename R, bool LAB, bool EX, bool VEC = false>
+template <int S, typename R, bool LAB, bool EX, bool VEC = false, bool JP = false>
 __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
                                                unsigned long long *step_acc) {
     __shared__ double s_tab[4][2 * EPOCH_TAB_MAX];
@@ -917,7 +1002,8 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
     if (idx < npix) {
         const int pi = (int)(idx % v.width), pj = (int)(idx / v.width);
         double ext[3];
-        val = pixel_value<S, R, 0, LAB, EX, CELLS_PER_BATCH, VEC>(v, pi, pj, true, tab, ns, ext);
+        val = pixel_value<S, R, 0, LAB, EX, CELLS_PER_BATCH, VEC, JP>(v, pi, pj, true, tab, ns,
+                                                                      ext);
         store_pixel(v, pi, pj, val);
         if constexpr (VEC)
             for (int c = 1; c < v.n_chan; c++) store_pixel(v, pi, pj, ext[c - 1], c);
@@ -936,7 +1022,8 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
 // n_queues), which under
 // round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
 // the other chunks when its own runs dry.
-template <int S, typename R, int SYNC, bool LAB, bool EX, int K, bool VEC = false>
+template <int S, typename R, int SYNC, bool LAB, bool EX, int K, bool VEC = false,
+          bool JP = false>
 __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
                                                const RayView *__restrict__ views,
                                                const Tile *__restrict__ tiles) {
@@ -975,7 +1062,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
         uint32_t ns = 0;
         const bool in_image = pi < v.width && pj < v.height;
         double ext[3];
-        const double val = pixel_value<S, R, SYNC, LAB, EX, K, VEC>(
+        const double val = pixel_value<S, R, SYNC, LAB, EX, K, VEC, JP>(
             v, pi, pj, in_image, use_tab ? wave_tab : nullptr, ns, ext);
         if (in_image) {
             store_pixel(v, pi, pj, val);
@@ -993,11 +1080,12 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
 
 // Sample marking for the compulsory-bytes count (untimed instrumentation).
 template <int S, typename R>
-__global__ void __launch_bounds__(256) k_mark(RayView v, uint32_t *bitmap, int line_log2) {
+__global__ void __launch_bounds__(256) k_mark(RayView v, uint32_t *bitmap, int line_log2,
+                                              bool moving_only) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long npix = (long long)v.width * v.height;
     if (idx >= npix) return;
-    mark_ray<R>(v, (int)(idx % v.width), (int)(idx / v.width), bitmap, line_log2);
+    mark_ray<S, R>(v, (int)(idx % v.width), (int)(idx / v.width), bitmap, line_log2, moving_only);
 }
 
 __global__ void __launch_bounds__(256) k_popcount(const uint32_t *bm, uint64_t words,
@@ -1021,6 +1109,15 @@ __global__ void __launch_bounds__(256) k_pack_j(const typename RecT<S>::raw *__r
         if constexpr (S == ST_F64 || S == ST_F32) out[i] = rec[i].x;
         else out[i] = (unsigned short)(rec[i].x & 0xffffu);
     }
+}
+
+template <int S>
+__global__ void __launch_bounds__(256) k_pack_jplane(const typename RecT<S>::raw *__restrict__ rec,
+                                                     typename JFieldT<S>::raw *__restrict__ out,
+                                                     uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = jplane_element<S>(rec[i]);
 }
 
 __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long *p, uint64_t n,
@@ -1176,6 +1273,14 @@ static hipError_t plain_impl(const RayView &v, double *flux_acc, unsigned long l
                              hipStream_t s) {
     const dim3 g((unsigned)(((uint64_t)v.width * v.height + 255) / 256)), b(256);
     const bool lab = v.n_blocks > 0, ex = (v.flags & F_EXACT) != 0;
+    if constexpr (S != ST_F64) {
+        // (the planner gives an emissivity plane only to plain stacks)
+        if (v.st.jplane && !lab && v.n_chan == 1) {
+            if (ex) hipLaunchKernelGGL((k_plain<S, R, false, true, false, true>), g, b, 0, s, v, flux_acc, step_acc);
+            else hipLaunchKernelGGL((k_plain<S, R, false, false, false, true>), g, b, 0, s, v, flux_acc, step_acc);
+            return hipGetLastError();
+        }
+    }
     if (v.n_chan > 1) hipLaunchKernelGGL((k_plain<S, R, false, false, true>), g, b, 0, s, v, flux_acc, step_acc);
     else if (lab && ex) hipLaunchKernelGGL((k_plain<S, R, true, true>), g, b, 0, s, v, flux_acc, step_acc);
     else if (lab) hipLaunchKernelGGL((k_plain<S, R, true, false>), g, b, 0, s, v, flux_acc, step_acc);
@@ -1199,13 +1304,15 @@ hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *
     return hipErrorInvalidValue;
 }
 
-template <int S, typename R, int SYNC, bool LAB, bool EX>
+template <int S, typename R, int SYNC, bool LAB, bool EX, bool JP = false>
 static void batch_launch_k(const BatchLaunch &bl, bool k8, int grid_blocks, hipStream_t s) {
     const dim3 g((unsigned)grid_blocks), b(256);
     if (k8)
-        hipLaunchKernelGGL((k_batch<S, R, SYNC, LAB, EX, 8>), g, b, 0, s, bl, bl.views, bl.tiles);
+        hipLaunchKernelGGL((k_batch<S, R, SYNC, LAB, EX, 8, false, JP>), g, b, 0, s, bl, bl.views,
+                           bl.tiles);
     else
-        hipLaunchKernelGGL((k_batch<S, R, SYNC, LAB, EX, 4>), g, b, 0, s, bl, bl.views, bl.tiles);
+        hipLaunchKernelGGL((k_batch<S, R, SYNC, LAB, EX, 4, false, JP>), g, b, 0, s, bl, bl.views,
+                           bl.tiles);
 }
 
 template <int S, typename R>
@@ -1222,6 +1329,18 @@ static hipError_t batch_impl(const BatchLaunch &bl, int variant, int grid_blocks
             hipLaunchKernelGGL((k_batch<S, R, 0, false, false, 4, true>), g, b, 0, s, bl, bl.views,
                                bl.tiles);
         return hipGetLastError();
+    }
+    if constexpr (S != ST_F64) {
+        if (variant & KV_JP) {
+            switch (variant & 7) {
+                case 0: batch_launch_k<S, R, 0, false, false, true>(bl, k8, grid_blocks, s); break;
+                case 1: batch_launch_k<S, R, 1, false, false, true>(bl, k8, grid_blocks, s); break;
+                case 4: batch_launch_k<S, R, 0, false, true, true>(bl, k8, grid_blocks, s); break;
+                case 5: batch_launch_k<S, R, 1, false, true, true>(bl, k8, grid_blocks, s); break;
+                default: return hipErrorInvalidValue;  // (labelled stacks read whole records)
+            }
+            return hipGetLastError();
+        }
     }
     switch (variant & 7) {
         case 0: batch_launch_k<S, R, 0, false, false>(bl, k8, grid_blocks, s); break;
@@ -1251,23 +1370,26 @@ hipError_t launch_batch(int store, bool f64, int variant, const BatchLaunch &bl,
 }
 
 template <int S, typename R>
-static hipError_t mark_impl(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s) {
+static hipError_t mark_impl(const RayView &v, uint32_t *bitmap, int line_log2, bool moving_only,
+                            hipStream_t s) {
     const uint64_t npix = (uint64_t)v.width * v.height;
     hipLaunchKernelGGL((k_mark<S, R>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, v,
-                       bitmap, line_log2);
+                       bitmap, line_log2, moving_only);
     return hipGetLastError();
 }
 
-hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, hipStream_t s) {
+hipError_t launch_mark(const RayView &v, uint32_t *bitmap, int line_log2, bool moving_only,
+                       hipStream_t s) {
     const bool f64 = (v.flags & F_F64_DDA) != 0;
+    const bool mo = moving_only;
     switch (v.st.store) {
-        case ST_F64: return mark_impl<ST_F64, double>(v, bitmap, line_log2, s);
-        case ST_F32: return f64 ? mark_impl<ST_F32, double>(v, bitmap, line_log2, s)
-                                : mark_impl<ST_F32, float>(v, bitmap, line_log2, s);
-        case ST_F16: return f64 ? mark_impl<ST_F16, double>(v, bitmap, line_log2, s)
-                                : mark_impl<ST_F16, float>(v, bitmap, line_log2, s);
-        case ST_BF16: return f64 ? mark_impl<ST_BF16, double>(v, bitmap, line_log2, s)
-                                 : mark_impl<ST_BF16, float>(v, bitmap, line_log2, s);
+        case ST_F64: return mark_impl<ST_F64, double>(v, bitmap, line_log2, mo, s);
+        case ST_F32: return f64 ? mark_impl<ST_F32, double>(v, bitmap, line_log2, mo, s)
+                                : mark_impl<ST_F32, float>(v, bitmap, line_log2, mo, s);
+        case ST_F16: return f64 ? mark_impl<ST_F16, double>(v, bitmap, line_log2, mo, s)
+                                : mark_impl<ST_F16, float>(v, bitmap, line_log2, mo, s);
+        case ST_BF16: return f64 ? mark_impl<ST_BF16, double>(v, bitmap, line_log2, mo, s)
+                                 : mark_impl<ST_BF16, float>(v, bitmap, line_log2, mo, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1380,6 +1502,27 @@ hipError_t launch_pack_j(int store, const void *records, void *out, uint64_t n, 
             break;
         case ST_BF16:
             hipLaunchKernelGGL(k_pack_j<ST_BF16>, g, b, 0, s, (const rec_h16 *)records,
+                               (unsigned short *)out, n);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_jplane(int store, const void *records, void *out, uint64_t n,
+                              hipStream_t s) {
+    const dim3 g(grid_for(n, 1u << 15)), b(256);
+    switch (store) {
+        case ST_F32:
+            hipLaunchKernelGGL(k_pack_jplane<ST_F32>, g, b, 0, s, (const rec_f32 *)records,
+                               (float *)out, n);
+            break;
+        case ST_F16:
+            hipLaunchKernelGGL(k_pack_jplane<ST_F16>, g, b, 0, s, (const rec_h16 *)records,
+                               (unsigned short *)out, n);
+            break;
+        case ST_BF16:
+            hipLaunchKernelGGL(k_pack_jplane<ST_BF16>, g, b, 0, s, (const rec_h16 *)records,
                                (unsigned short *)out, n);
             break;
         default: return hipErrorInvalidValue;

@@ -94,9 +94,16 @@ extern "C" dart_status dart_render_batch_noalloc(const dart_stack *const *stacks
                             dst[k].second);
     }
     hipStream_t stream = (hipStream_t)hip_stream;
+    dart_status st = DART_OK;
+    for (int32_t i = 0; i < n; i++) {
+        st = refresh_vector(stacks[i], stream);
+        // (an emissivity plane is repacked in place, never allocated here)
+        if (st == DART_OK) st = refresh_jplane(stacks[i], stream, false);
+        if (st != DART_OK) return st;
+    }
     const dart_tuning tun = tuning_for(stacks[0]);
     std::vector<Group> groups;
-    dart_status st = plan_batch(stacks, views, n, images, tun, groups);
+    st = plan_batch(stacks, views, n, images, tun, groups);
     if (st != DART_OK) return st;
     size_t nv = 0, nt = 0;
     assign_offsets(groups, &nv, &nt);
@@ -108,10 +115,6 @@ extern "C" dart_status dart_render_batch_noalloc(const dart_stack *const *stacks
                     "%d views in %zu tiles need %zu bytes of scratch; the fixed scratch holds %zu "
                     "(use dart_render_batch, or fewer or smaller views per call)",
                     n, nt, desc_off + desc_bytes, (size_t)DART_NOALLOC_SCRATCH_BYTES);
-    for (int32_t i = 0; i < n; i++) {
-        st = refresh_vector(stacks[i], stream);
-        if (st != DART_OK) return st;
-    }
     int device = 0;
     HIP_TRY_STATUS(hipGetDevice(&device), "hipGetDevice");
     DeviceScratch *sc = nullptr;

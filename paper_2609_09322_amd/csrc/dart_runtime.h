@@ -45,6 +45,11 @@ struct dart_stack {
     std::vector<dart_stack *> comps;
     void *packed = nullptr;             // emissivity of components 1.., packed (device)
     std::vector<uint64_t> packed_gen;   // the components' generations when packed
+    // emissivity plane (StackDev::jplane) of a plain FP32 / 16-bit stack: built
+    // at the first render after the records change, when memory allows
+    void *jplane = nullptr;
+    uint64_t jplane_bytes = 0;
+    uint64_t jplane_gen = 0;            // the generation it was packed from (0: never)
     bool vector() const { return !comps.empty(); }
     int channels() const { return comps.empty() ? 1 : (int)comps.size(); }
 };
@@ -56,6 +61,10 @@ dart_status hip_fail(hipError_t e, const char *what);
 int device_cus(int dev);
 uint32_t record_bytes(int store);
 dart_status resolve_view(const dart_stack *s, const dart_view *v, RayView *rv);
+// Packs the stack's emissivity plane when it is missing or stale (allocating it
+// only if may_alloc); a stack without one is rendered from whole records.
+dart_status refresh_jplane(const dart_stack *s, hipStream_t stream, bool may_alloc);
+bool jplane_ready(const dart_stack *s);
 void note_use(const dart_stack *s, hipStream_t stream);
 bool stack_busy(const dart_stack *s);
 dart_tuning tuning_for(const dart_stack *s);
@@ -71,6 +80,7 @@ struct Group {
     bool labelled = false;  // views of labelled stacks (kernels with the block loop)
     bool vec = false;       // views of vector stacks
     bool exact = false;     // views with exact temporal integration
+    bool jp = false;        // views that read their stacks' emissivity planes
     std::vector<RayView> views;
     std::vector<Tile> tiles;
     size_t view_off = 0, tile_off = 0;  // offsets in the uploaded descriptor arrays

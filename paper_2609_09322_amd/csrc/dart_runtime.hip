@@ -344,6 +344,7 @@ extern "C" dart_status dart_free_epochs(dart_stack *s) {
     } else {
         (void)hipFree((void *)s->dev.data);
         (void)hipFree((void *)s->dev.times);
+        if (s->jplane) (void)hipFree(s->jplane);
     }
     delete s;
     return DART_OK;
@@ -490,7 +491,7 @@ extern "C" dart_status dart_stack_get_info(const dart_stack *s, dart_stack_info 
     }
     info->n_epochs = s->dev.n_epochs;
     info->storage = s->storage;
-    info->device_bytes = s->bytes;
+    info->device_bytes = s->bytes + s->jplane_bytes;
     return DART_OK;
 }
 
@@ -665,7 +666,7 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
         return fail(DART_E_INVAL, "FP64 images need an FP64 stack");
     if (v->flags & ~(uint32_t)(DART_NO_LOOKBACK | DART_NO_BEAMING | DART_NEAREST_EPOCH |
                                DART_NO_KAHAN | DART_FORCE_F64_DDA | DART_DEVICE_PTRS |
-                               DART_ACCUMULATE | DART_EXACT_TIME))
+                               DART_ACCUMULATE | DART_EXACT_TIME | DART_RECORDS_ONLY))
         return fail(DART_E_INVAL, "unknown view flags 0x%x", v->flags);
     if ((v->flags & DART_EXACT_TIME) && (v->flags & DART_NEAREST_EPOCH))
         return fail(DART_E_INVAL, "DART_EXACT_TIME integrates the linear interpolation; "
@@ -714,6 +715,7 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     rv->height = v->height;
     rv->out_f64 = v->out_dtype == DART_F64;
     rv->st = s->dev;
+    rv->st.jplane = (!(v->flags & DART_RECORDS_ONLY) && jplane_ready(s)) ? s->jplane : nullptr;
     rv->blocks = s->dev_blocks;
     rv->n_blocks = (int32_t)s->parts.size();
     rv->n_chan = s->channels();
@@ -824,10 +826,12 @@ hipError_t dart::ws_reserve(Workspace *ws, size_t n_views, size_t n_tiles, size_
 extern "C" dart_status dart_render(const dart_stack *s, const dart_view *v, void *image,
                                    double *flux_out, uint64_t *steps_out, void *hip_stream) {
     if (!image) return fail(DART_E_INVAL, "image is NULL");
-    RayView rv;
-    dart_status st = resolve_view(s, v, &rv);
-    if (st != DART_OK) return st;
     hipStream_t stream = (hipStream_t)hip_stream;
+    dart_status st = refresh_jplane(s, stream, true);
+    if (st != DART_OK) return st;
+    RayView rv;
+    st = resolve_view(s, v, &rv);
+    if (st != DART_OK) return st;
     st = refresh_vector(s, stream);
     if (st != DART_OK) return st;
     Workspace *ws = get_workspace(stream);
@@ -909,6 +913,55 @@ dart_status dart::refresh_vector(const dart_stack *cs, hipStream_t stream) {
     return DART_OK;
 }
 
+// The emissivity plane serves plain stacks with FP32 or 16-bit records (FP64
+// records stay whole; labelled and vector stacks read their parts' records;
+// streamed windows have no plane).
+static bool jplane_eligible(const dart_stack *s) {
+    return s && !s->labelled() && !s->vector() && s->dev.store != ST_F64 &&
+           s->dev.epoch_stride > 0;
+}
+
+bool dart::jplane_ready(const dart_stack *s) {
+    return jplane_eligible(s) && s->jplane && s->jplane_gen == s->generation;
+}
+
+dart_status dart::refresh_jplane(const dart_stack *cs, hipStream_t stream, bool may_alloc) {
+    if (!jplane_eligible(cs)) return DART_OK;
+    dart_stack *s = const_cast<dart_stack *>(cs);
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->jplane && s->jplane_gen == s->generation) return DART_OK;
+    for (char f : s->filled)
+        if (!f) return DART_OK;  // (such a stack is not rendered)
+    // nothing is packed into a graph the caller is capturing: its renders read
+    // whole records until a render outside capture packs the plane
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cap), "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone) return DART_OK;
+    const uint64_t n = (uint64_t)s->dev.epoch_stride * s->dev.n_epochs;
+    const uint64_t need = n * (record_bytes(s->dev.store) / 4);
+    if (s->jplane_bytes != need && !may_alloc) return DART_OK;
+    // renders still reading the old plane must finish first
+    for (auto &u : s->uses) HIP_TRY(hipEventSynchronize(u.second), "wait for renders");
+    if (s->jplane_bytes != need) {
+        if (s->jplane) (void)hipFree(s->jplane);
+        s->jplane = nullptr;
+        s->jplane_bytes = 0;
+        void *p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            (void)hipGetLastError();  // no room: renders read whole records
+            return DART_OK;
+        }
+        s->jplane = p;
+        s->jplane_bytes = need;
+    }
+    HIP_TRY(launch_pack_jplane(s->dev.store, s->dev.data, s->jplane, n, stream),
+            "pack emissivity plane");
+    // complete before a render on any stream reads it
+    HIP_TRY(hipStreamSynchronize(stream), "sync");
+    s->jplane_gen = s->generation;
+    return DART_OK;
+}
+
 dart_tuning dart::tuning_for(const dart_stack *s) {
     if (s && s->tuned) return s->tuning;
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -968,8 +1021,9 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         if (!images[i]) return fail(DART_E_INVAL, "images[%d] is NULL", i);
         rv.image = images[i];
         rv.acc_index = i;
-        const int key = rv.st.store * 16 + (rv.n_chan > 1 ? 8 : 0) + ((rv.flags & F_F64_DDA) ? 4 : 0) +
-                        (rv.n_blocks > 0 ? 2 : 0) + ((rv.flags & F_EXACT) ? 1 : 0);
+        const int key = (rv.st.jplane ? 64 : 0) + rv.st.store * 16 + (rv.n_chan > 1 ? 8 : 0) +
+                        ((rv.flags & F_F64_DDA) ? 4 : 0) + (rv.n_blocks > 0 ? 2 : 0) +
+                        ((rv.flags & F_EXACT) ? 1 : 0);
         auto it = gindex.find(key);
         if (it == gindex.end()) {
             it = gindex.emplace(key, groups.size()).first;
@@ -979,6 +1033,7 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             groups.back().labelled = rv.n_blocks > 0;
             groups.back().exact = (rv.flags & F_EXACT) != 0;
             groups.back().vec = rv.n_chan > 1;
+            groups.back().jp = rv.st.jplane != nullptr;
         }
         Group &g = groups[it->second];
         const uint32_t vi = (uint32_t)g.views.size();
@@ -1139,6 +1194,7 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
         const int variant = g.vec ? (KV_VEC | (tun.cells_per_batch == 8 ? KV_K8 : 0))
                                   : (tun.depth_sync > 0 ? KV_SYNC : 0) |
                                         (g.labelled ? KV_LABELLED : 0) | (g.exact ? KV_EXACT : 0) |
+                                        (g.jp ? KV_JP : 0) |
                                         (tun.cells_per_batch == 8 ? KV_K8 : 0);
         e = launch_batch(g.store, g.f64, variant, bl, blocks, stream);
         if (e != hipSuccess) return e;
@@ -1202,6 +1258,7 @@ extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const 
     }
     for (int32_t i = 0; i < n; i++) {
         dart_status st = refresh_vector(stacks[i], stream);
+        if (st == DART_OK) st = refresh_jplane(stacks[i], stream, true);
         if (st != DART_OK) return st;
     }
     const dart_tuning tun = tuning_for(stacks[0]);
@@ -1219,6 +1276,8 @@ extern "C" dart_status dart_render_batch(const dart_stack *const *stacks, const 
     for (int32_t i = 0; i < n; i++) {
         put(&stacks[i], sizeof(void *));
         put(&stacks[i]->generation, sizeof(stacks[i]->generation));
+        const uint8_t jp = jplane_ready(stacks[i]) ? 1 : 0;
+        put(&jp, 1);
         put(&views[i], sizeof(dart_view));
         put(&images[i], sizeof(void *));
     }
@@ -1520,7 +1579,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
 // Distinct marked bits over one view: records (line_log2 < 0) or 128-byte
 // lines of the resident layout (2^line_log2 records each).
 static dart_status count_marked(const dart_stack *s, const dart_view *v, int line_log2,
-                                uint64_t *out, void *hip_stream) {
+                                bool moving_only, uint64_t *out, void *hip_stream) {
     if (!out) return fail(DART_E_INVAL, "output pointer is NULL");
     if (s && s->labelled()) return fail(DART_E_INVAL, "count the sub-domains of a labelled stack");
     RayView rv;
@@ -1536,7 +1595,7 @@ static dart_status count_marked(const dart_stack *s, const dart_view *v, int lin
     HIP_TRY(hipMalloc(&bm, u64s * 8), "hipMalloc(bitmap)");
     unsigned long long *cnt = bm + (u64s - 1);
     hipError_t e = launch_fill_u64(bm, u64s, 0ull, stream);
-    if (e == hipSuccess) e = launch_mark(rv, (uint32_t *)bm, line_log2, stream);
+    if (e == hipSuccess) e = launch_mark(rv, (uint32_t *)bm, line_log2, moving_only, stream);
     if (e == hipSuccess) e = launch_popcount((const uint32_t *)bm, words, cnt, stream);
     unsigned long long c = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&c, cnt, sizeof(c), hipMemcpyDeviceToHost, stream);
@@ -1549,7 +1608,7 @@ static dart_status count_marked(const dart_stack *s, const dart_view *v, int lin
 
 extern "C" dart_status dart_count_samples(const dart_stack *s, const dart_view *v,
                                           uint64_t *samples_out, void *hip_stream) {
-    return count_marked(s, v, -1, samples_out, hip_stream);
+    return count_marked(s, v, -1, false, samples_out, hip_stream);
 }
 
 extern "C" dart_status dart_count_lines(const dart_stack *s, const dart_view *v,
@@ -1558,7 +1617,43 @@ extern "C" dart_status dart_count_lines(const dart_stack *s, const dart_view *v,
     const uint32_t rb = record_bytes(s->dev.store);
     int line_log2 = 0;
     while ((rb << (line_log2 + 1)) <= 128u) line_log2++;
-    return count_marked(s, v, line_log2, lines_out, hip_stream);
+    return count_marked(s, v, line_log2, false, lines_out, hip_stream);
+}
+
+extern "C" dart_status dart_count_bytes(const dart_stack *s, const dart_view *v,
+                                        uint64_t *compulsory_out, uint64_t *line_bytes_out,
+                                        void *hip_stream) {
+    if (!s || !v) return fail(DART_E_INVAL, "NULL argument");
+    if (s->labelled()) return fail(DART_E_INVAL, "count the sub-domains of a labelled stack");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    dart_status st = refresh_jplane(s, stream, true);
+    if (st != DART_OK) return st;
+    const uint32_t rb = record_bytes(s->dev.store);
+    auto lines_of = [](uint32_t elem) {
+        int l = 0;
+        while ((elem << (l + 1)) <= 128u) l++;
+        return l;
+    };
+    const bool plane = !(v->flags & DART_RECORDS_ONLY) && jplane_ready(s);
+    uint64_t samples = 0, lines = 0;
+    st = count_marked(s, v, -1, false, &samples, hip_stream);
+    if (st == DART_OK && line_bytes_out)
+        st = count_marked(s, v, lines_of(plane ? rb / 4 : rb), false, &lines, hip_stream);
+    if (st != DART_OK) return st;
+    uint64_t comp = samples * (plane ? rb / 4 : rb), lb = lines * 128;
+    if (plane) {
+        // samples marked to be read whole cost their records as well
+        uint64_t whole = 0, wlines = 0;
+        st = count_marked(s, v, -1, true, &whole, hip_stream);
+        if (st == DART_OK && line_bytes_out)
+            st = count_marked(s, v, lines_of(rb), true, &wlines, hip_stream);
+        if (st != DART_OK) return st;
+        comp += whole * rb;
+        lb += wlines * 128;
+    }
+    if (compulsory_out) *compulsory_out = comp;
+    if (line_bytes_out) *line_bytes_out = lb;
+    return DART_OK;
 }
 
 // Read-only bandwidth probe: every 16-byte word of src is loaded once and

@@ -464,8 +464,12 @@ extern "C" dart_status dart_server_create(size_t hbm_budget_bytes, int32_t max_i
 extern "C" dart_status dart_submit(dart_server *srv, const dart_stack *s, const dart_view *v,
                                    void *image, uint64_t *ticket) {
     if (!srv || !s || !v || !image || !ticket) return fail(DART_E_INVAL, "NULL argument");
+    // (the stack's emissivity plane is packed here, in the caller's thread,
+    // when the records changed since it was last packed)
+    dart_status st = refresh_jplane(s, nullptr, true);
+    if (st != DART_OK) return st;
     RayView rv;
-    dart_status st = resolve_view(s, v, &rv);
+    st = resolve_view(s, v, &rv);
     if (st != DART_OK) return st;
     if (v->out_dtype != DART_F32) return fail(DART_E_INVAL, "the server renders float32 images");
     if (s->vector()) return fail(DART_E_INVAL, "the server does not render vector stacks");

@@ -29,6 +29,7 @@ DART_DEVICE_PTRS = 0x20
 DART_KERNEL_PLAIN = 0x40
 DART_ACCUMULATE = 0x80
 DART_EXACT_TIME = 0x100
+DART_RECORDS_ONLY = 0x200
 
 EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "dart_free_epochs",
            "dart_stack_get_info", "dart_stack_read_epoch", "dart_stack_rebrick", "dart_stack_set_placement",
@@ -36,6 +37,7 @@ EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "da
            "dart_streamer_render",
            "dart_streamer_get_stats", "dart_streamer_destroy", "dart_render", "dart_render_batch",
            "dart_render_batch_noalloc", "dart_autotune", "dart_set_tuning", "dart_get_tuning", "dart_count_samples", "dart_count_lines",
+           "dart_count_bytes",
            "dart_record_bytes", "dart_bandwidth_probe", "dart_gather_probe", "dart_server_create", "dart_submit",
            "dart_poll", "dart_wait", "dart_server_destroy", "dart_server_get_stats",
            "dart_server_get_timeline",
@@ -136,6 +138,7 @@ def _load():
         "dart_get_tuning": [_P],
         "dart_count_samples": [_P, _P, _P, _P],
         "dart_count_lines": [_P, _P, _P, _P],
+        "dart_count_bytes": [_P, _P, _P, _P, _P],
         "dart_record_bytes": [_P, _P],
         "dart_bandwidth_probe": [_P, _P, U64, I32, _P],
         "dart_gather_probe": [_P, U64, I32, _P],
@@ -415,6 +418,15 @@ def dart_count_samples(stack: Stack, view: View, stream=None) -> int:
     _check(_load().dart_count_samples(stack.handle, ctypes.byref(view.c()), ctypes.byref(n),
                                       _stream(stream)))
     return n.value
+
+
+def dart_count_bytes(stack: Stack, view: View, stream=None):
+    """(compulsory bytes, line bytes) of a render of the view as renders read
+    the stack (its emissivity plane when it has one), images excluded."""
+    c, l = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(_load().dart_count_bytes(stack.handle, ctypes.byref(view.c()), ctypes.byref(c),
+                                    ctypes.byref(l), _stream(stream)))
+    return c.value, l.value
 
 
 def dart_count_lines(stack: Stack, view: View, stream=None) -> int:
