@@ -355,14 +355,20 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
     cell_steps = int(np.sum(steps))
     samples = [dart.dart_count_samples(st, v, stream) for v in views] if not args.profile else []
     out_bytes = sum(4 * v.width * v.height for v in views)
+    # compulsory bytes as the metric defines them: distinct positive-weight
+    # (cell, epoch) samples x record bytes + images; and the bytes renders of
+    # this layout must read (emissivity plane, whole records where marked)
+    compulsory = (sum(samples) * rec_bytes + out_bytes) if samples else None
+    lines = [dart.dart_count_lines(st, v, stream) for v in views] if not args.profile else []
+    line_bytes = (sum(lines) * 128 + out_bytes) if lines else None
     counted = [dart.dart_count_bytes(st, v, stream) for v in views] if not args.profile else []
-    compulsory = (sum(c for c, _ in counted) + out_bytes) if counted else None
-    line_bytes = (sum(l for _, l in counted) + out_bytes) if counted else None
-    record_bytes = (sum(samples) * rec_bytes + out_bytes) if samples else None
+    plane_bytes = (sum(c for c, _ in counted) + out_bytes) if counted else None
+    plane_lines = (sum(l for _, l in counted) + out_bytes) if counted else None
     # (renders read an emissivity plane when the counted bytes fall below whole records)
-    plane = bool(counted) and sum(c for c, _ in counted) < sum(samples) * rec_bytes
+    plane = bool(counted) and plane_bytes < compulsory
     log(f"{n_img} images, {cell_steps:.4e} cell-steps per step, samples {sum(samples) if samples else 'n/a'}, "
-        f"compulsory {compulsory}, line bytes {line_bytes}, emissivity plane {plane}")
+        f"compulsory {compulsory}, line bytes {line_bytes}, emissivity plane {plane} "
+        f"(bytes {plane_bytes}, line bytes {plane_lines})")
 
     def batched():
         dart.dart_render_batch(stacks, views, imgs, stream=stream, stats=False)
@@ -387,7 +393,6 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
         ro = {"ms_per_step": 1e3 * rwall / args.steps, "kernel_ms": float(np.mean(rper)),
               "images_per_s": n_img / rwall * args.steps,
               "identical_images": bool(all(torch.equal(a, b) for a, b in zip(imgs, ro_imgs))),
-              "compulsory_bytes": record_bytes,
               "note": "the same batched call with DART_RECORDS_ONLY: whole records for every "
                       "cell instead of the emissivity plane"}
         log(f"records only: {ro}")
@@ -489,13 +494,18 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
                 "traffic_gbs": traffic / (kernel_ms * 1e-3) / 1e9 if traffic else None,
                 "kernel": "k_batch (persistent tile-queue render)",
                 "bytes_per_launch": compulsory,
-                "bytes_definition": ("distinct (cell, epoch) samples with positive weight x "
-                                     "(emissivity-plane value + the whole record for samples "
-                                     "marked to be read whole) + image bytes" if plane else
-                                     "distinct (cell, epoch) records with positive weight x record "
-                                     "bytes + image bytes"),
-                "record_bytes_per_launch": record_bytes,
-                "record_bytes_gbs": record_bytes / (kernel_ms * 1e-3) / 1e9 if record_bytes else None,
+                "bytes_definition": "distinct (cell, epoch) records with positive weight x record "
+                                    "bytes + image bytes",
+                "emissivity_plane": plane,
+                "plane_bytes_per_launch": plane_bytes if plane else None,
+                "plane_bytes_definition": "the bytes a render of this layout must read: one "
+                                          "emissivity-plane value per positive-weight sample, "
+                                          "+ the whole record where marked (velocity), + images; "
+                                          "with the plane, achieved counts record bytes the "
+                                          "kernel does not move, so traffic (counters) is the "
+                                          "HBM truth",
+                "plane_gbs": plane_bytes / (kernel_ms * 1e-3) / 1e9 if plane else None,
+                "plane_line_bytes_per_launch": plane_lines if plane else None,
                 "measured_copy_gbs": bw,
                 "frac_of_measured_copy": (achieved / bw) if bw else None,
                 "measured_read_gbs": rd,
@@ -508,10 +518,9 @@ def run_render_workload(args, dart, torch, name, dims, n_epochs, storage, views_
                 if (traffic and gp) else None,
                 "gather_bytes_gbs": cell_steps * 2 * rec_bytes / (kernel_ms * 1e-3) / 1e9,
                 "line_bytes_per_launch": line_bytes,
-                "line_bytes_definition": "distinct 128-B lines of the resident layout (plane and "
-                                         "records) holding those bytes x 128 + image bytes (the "
-                                         "fewest bytes a line-granular fetch of this layout can "
-                                         "move)",
+                "line_bytes_definition": "distinct 128-B lines of the resident records holding "
+                                         "those records x 128 + image bytes (the fewest bytes a "
+                                         "line-granular fetch of whole records can move)",
                 "line_gbs": line_bytes / (kernel_ms * 1e-3) / 1e9 if line_bytes else None}
     value = cell_steps / (ms_step * 1e-3)
     line = {
@@ -722,11 +731,13 @@ def run_serve_workload(args, dart, torch):
         dart.dart_render(s, v, imgs[q], stream=stream, stats=False)
     torch.cuda.synchronize()
     plain_wall = time.perf_counter() - p0
-    # compulsory bytes of the saturation requests (as renders read the stacks) + images
-    comp = 0
+    # compulsory bytes of the saturation requests (records + images), and the
+    # bytes renders of the resident layout must read (emissivity plane)
+    comp, comp_plane = 0, 0
     for q in range(sat_n):
         s, v = reqs[q]
-        comp += dart.dart_count_bytes(s, v, stream)[0] + 4 * v.width * v.height
+        comp += dart.dart_count_samples(s, v, stream) * 8 + 4 * v.width * v.height
+        comp_plane += dart.dart_count_bytes(s, v, stream)[0] + 4 * v.width * v.height
     achieved = comp / sat_wall / 1e9
     cpu = None if args.no_cpu_baseline else served_cpu_baseline(dart, torch, stacks, reqs)
     return {
@@ -755,10 +766,13 @@ def run_serve_workload(args, dart, torch):
                      "traffic_source": "no counter run of the served mix",
                      "bytes_per_launch": None,
                      "bytes_definition": "compulsory bytes of the %d saturation requests "
-                                         "(distinct positive-weight samples x 2 B emissivity-plane "
-                                         "value, + 8 B records where marked to be read whole, + "
-                                         "images) over their wall time, host scheduling "
-                                         "included" % sat_n},
+                                         "(distinct positive-weight records x 8 B + images) over "
+                                         "their wall time, host scheduling included" % sat_n,
+                     "plane_bytes": comp_plane,
+                     "plane_gbs": comp_plane / sat_wall / 1e9,
+                     "plane_bytes_definition": "the bytes renders of the resident layout must "
+                                               "read: 2 B emissivity-plane value per sample, + "
+                                               "8 B records where marked, + images"},
         "waves": int(stats.waves), "max_wave_requests": int(stats.max_wave_requests),
         "timeline_poisson": timeline_delta(tl0, tl1),
         "timeline_saturation": timeline_delta(tl2, tl3),
@@ -879,9 +893,12 @@ def run_large_workload(args, dart, torch):
     pwall, _ = time_steps(torch, stream, plain, max(1, args.steps // 2), 1)
     pms = 1e3 * pwall / max(1, args.steps // 2)
     log(f"batched {ms_step:.1f} ms/step, plain {pms:.1f} ms/step, {cell_steps:.3e} cell-steps")
+    samples = [dart.dart_count_samples(st, v, stream) for v in views[:4]]
+    est_compulsory = (sum(samples) / 4 * n) * 8 + n * 4 * 1024 * 1024
+    lines = [dart.dart_count_lines(st, v, stream) for v in views[:4]]
+    est_lines = (sum(lines) / 4 * n) * 128 + n * 4 * 1024 * 1024
     counted = [dart.dart_count_bytes(st, v, stream) for v in views[:4]]
-    est_compulsory = (sum(c for c, _ in counted) / 4 * n) + n * 4 * 1024 * 1024
-    est_lines = (sum(l for _, l in counted) / 4 * n) + n * 4 * 1024 * 1024
+    est_plane = (sum(c for c, _ in counted) / 4 * n) + n * 4 * 1024 * 1024
     acc, cpu = None, None
     if args.check:
         t1 = time.time()
@@ -940,8 +957,12 @@ def run_large_workload(args, dart, torch):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tsrc,
                      "l2_hit_rate": l2_hit,
                      "bytes_per_launch": est_compulsory,
-                     "bytes_definition": "compulsory bytes (emissivity-plane values, + whole "
-                                         "records where marked) estimated from 4 counted views",
+                     "bytes_definition": "compulsory records estimated from 4 counted views",
+                     "plane_bytes_per_launch": est_plane,
+                     "plane_gbs": est_plane / (float(np.mean(per)) * 1e-3) / 1e9,
+                     "plane_bytes_definition": "the bytes renders of the resident layout must "
+                                               "read (emissivity plane, whole records where "
+                                               "marked), estimated from the same 4 views",
                      "line_bytes_per_launch": est_lines,
                      "line_gbs": est_lines / (float(np.mean(per)) * 1e-3) / 1e9},
         "accuracy": acc, "tuning": tuning, "cpu_baseline": cpu, "slabs": slabs,

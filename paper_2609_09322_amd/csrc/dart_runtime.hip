@@ -1418,18 +1418,23 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
             for (int order : orders)
                 for (int orient = 0; orient < 2; orient++)
                     cands.push_back({sh[0], sh[1], w, order, orient, 0, 8});
-    // Brick candidates: every power-of-two shape holding one 128-B cache line
-    // of records.  Which one wins depends on the view set: lines that extend
-    // along the rays' directions are used whole by one ray, lines across the
-    // image plane are only partly covered when rays are sparser than cells.
+    // Brick candidates: every power-of-two shape (sides up to 16) holding one
+    // 128-B cache line of records, and, for stacks with an emissivity plane
+    // (which renders read for the cells at rest), one line of the plane.
+    // Which one wins depends on the view set: lines that extend along the
+    // rays' directions are used whole by one ray, lines across the image plane
+    // are only partly covered when rays are sparser than cells.
     std::vector<std::array<int, 3>> bricks;
     if (rebrick) {
-        const int per_line = std::max(1u, 128u / record_bytes(stacks[0]->dev.store));
-        for (int bx = 1; bx <= per_line; bx *= 2)
-            for (int by = 1; bx * by <= per_line; by *= 2) {
-                const int bz = per_line / (bx * by);
-                if (bx * by * bz == per_line && bz <= 16) bricks.push_back({bx, by, bz});
-            }
+        const uint32_t rb = record_bytes(stacks[0]->dev.store);
+        std::vector<int> per_line = {(int)std::max(1u, 128u / rb)};
+        if (jplane_eligible(stacks[0])) per_line.push_back((int)(128u / (rb / 4)));
+        for (int pl : per_line)
+            for (int bx = 1; bx <= std::min(pl, 16); bx *= 2)
+                for (int by = 1; by <= 16 && bx * by <= pl; by *= 2) {
+                    const int bz = pl / (bx * by);
+                    if (bx * by * bz == pl && bz <= 16) bricks.push_back({bx, by, bz});
+                }
     } else {
         bricks = {{0, 0, 0}};
     }
