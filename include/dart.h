@@ -141,7 +141,7 @@ dart_status dart_free_epochs(dart_stack *s);
  * dart_render_batch_noalloc only into a plane already allocated).  The value's
  * sign bit marks records that must be read whole: any velocity bit set, or a
  * negative (or -0) emissivity.  A render reads the plane, and the whole records
- * only of the batches of cells where a contributing record carries the mark; a
+ * only of the batches of cells where a record carries the mark; a
  * jet's volume at rest is then read at a quarter of the bytes.  Images, flux
  * and cell-steps are bit for bit those of whole-record reads
  * (DART_RECORDS_ONLY).  Without room for the plane (hipMalloc fails) renders

@@ -164,9 +164,15 @@ __device__ __forceinline__ typename RecT<S>::val decode_j(typename JFieldT<S>::r
 // when the velocity bits are not all zero or j itself has its sign bit set
 // (negative, or -0).  An element without the mark is the record's j, exactly.
 template <int S>
-__device__ __forceinline__ uint32_t jplane_mark(typename JFieldT<S>::raw w) {
-    if constexpr (S == ST_F32) return __float_as_uint(w) >> 31;
-    else return (uint32_t)w >> 15;
+__device__ __forceinline__ uint32_t jplane_bits(typename JFieldT<S>::raw w) {
+    if constexpr (S == ST_F32) return __float_as_uint(w);
+    else return (uint32_t)w;
+}
+// the mark of an element, or of the OR of several elements' bits
+template <int S>
+__device__ __forceinline__ uint32_t jplane_mark(uint32_t bits) {
+    if constexpr (S == ST_F32) return bits >> 31;
+    else return (bits >> 15) & 1u;
 }
 template <int S>
 __device__ __forceinline__ typename JFieldT<S>::raw jplane_element(const typename RecT<S>::raw &r) {
@@ -520,7 +526,7 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
                 if constexpr (S == ST_F64) {
                     return beta_bits<S>(*rec) != 0u || signbit(rec->x);
                 } else {
-                    return jplane_mark<S>(jplane_element<S>(*rec)) != 0u;
+                    return jplane_mark<S>(jplane_bits<S>(jplane_element<S>(*rec))) != 0u;
                 }
             };
             if ((single || wt < (R)1) && (!moving_only || whole(m0))) {
@@ -762,22 +768,24 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
         Raw r0[K], r1[K];
         JF j0[K][NX], j1[K][NX];
         if constexpr (JP) {
-            // Emissivity elements first.  When no record that contributes to
-            // the batch, on any lane, carries the read-whole mark, every one of
-            // them is at rest with j >= 0 and the element is its j: the batch
-            // is consumed from the elements with the arithmetic of the at-rest
+            // Emissivity elements first.  When no element of the batch, on
+            // any lane, carries the read-whole mark, every record it reads is
+            // at rest with j >= 0 and the element is its j: the batch is
+            // consumed from the elements with the arithmetic of the at-rest
             // path below, and its sums are bit for bit those of the records.
+            // (Marks on cells that contribute nothing send the batch to the
+            // whole records too, which is never wrong, and saves a test per
+            // cell.)
             JF q0[K], q1[K];
 #pragma unroll
             for (int k = 0; k < K; k++) {
                 q0[k] = addr[k][0];
                 q1[k] = addr[k][second];
             }
-            uint32_t whole = 0u;
+            uint32_t any_bits = 0u;
 #pragma unroll
-            for (int k = 0; k < K; k++)
-                whole |= cds[k] != (A)0 ? (jplane_mark<S>(q0[k]) | jplane_mark<S>(q1[k])) : 0u;
-            if (!__any(whole != 0u)) {
+            for (int k = 0; k < K; k++) any_bits |= jplane_bits<S>(q0[k]) | jplane_bits<S>(q1[k]);
+            if (!__any(jplane_mark<S>(any_bits) != 0u)) {
 #pragma unroll
                 for (int k = 0; k < K; k++) {
                     A val = (A)decode_j<S>(q0[k]);
