@@ -132,5 +132,7 @@ hipError_t launch_pack_jplane(int store, const void *records, void *out, uint64_
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,
                            hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
+// Writes 0 to every pixel (and channel) of n tiles of the given views.
+hipError_t launch_clear_tiles(const RayView *views, const Tile *tiles, uint32_t n, hipStream_t s);
 
 }  // namespace dart

@@ -1086,6 +1086,23 @@ __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
     }
 }
 
+// Zero fill of the tiles a batch does not march (every ray of them misses the
+// grid): four 64-pixel tiles per 256-thread block, each lane one pixel in the
+// tile layout of k_batch, every channel.
+__global__ void __launch_bounds__(256) k_clear_tiles(const RayView *__restrict__ views,
+                                                     const Tile *__restrict__ tiles, uint32_t n) {
+    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= n) return;
+    const Tile tile = tiles[k];
+    const RayView &v = views[tile.view];
+    const int lane = threadIdx.x & 63;
+    const uint32_t tw_log2 = (uint32_t)v.tile_w_log2;
+    const int pi = (int)((uint32_t)tile.tx << tw_log2) + (lane & ((1 << tw_log2) - 1));
+    const int pj = (int)((uint32_t)tile.ty << (6 - tw_log2)) + (lane >> tw_log2);
+    if (pi < v.width && pj < v.height)
+        for (int c = 0; c < v.n_chan; c++) store_pixel(v, pi, pj, 0.0, c);
+}
+
 // Sample marking for the compulsory-bytes count (untimed instrumentation).
 template <int S, typename R>
 __global__ void __launch_bounds__(256) k_mark(RayView v, uint32_t *bitmap, int line_log2,
@@ -1535,6 +1552,11 @@ hipError_t launch_pack_jplane(int store, const void *records, void *out, uint64_
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_tiles(const RayView *views, const Tile *tiles, uint32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_tiles, dim3((n + 3) / 4), dim3(256), 0, s, views, tiles, n);
     return hipGetLastError();
 }
 

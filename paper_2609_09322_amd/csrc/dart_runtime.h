@@ -82,7 +82,11 @@ struct Group {
     bool exact = false;     // views with exact temporal integration
     bool jp = false;        // views that read their stacks' emissivity planes
     std::vector<RayView> views;
+    // queued tiles [0, q_begin[n_queues]), then n_clear tiles whose rays all
+    // miss the grid (their pixels are set to 0 by a fill kernel)
     std::vector<Tile> tiles;
+    std::vector<Tile> clear;  // (planner scratch)
+    uint32_t n_clear = 0;
     size_t view_off = 0, tile_off = 0;  // offsets in the uploaded descriptor arrays
     uint32_t n_queues = 8;
     uint32_t q_begin[MAX_QUEUES + 1] = {};  // chunk bounds in `tiles`

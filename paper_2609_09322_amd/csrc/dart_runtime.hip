@@ -986,6 +986,45 @@ static bool orient_flips(const RayView &rv, const dart_tuning &tun) {
     return elongated && long_u != axis_u;
 }
 
+// Rays of a view are parallel: the pixel ray at image-plane coordinates (u, w)
+// can meet the grid box only if (u, w) lies in the box's projection, which is
+// inside the bounding rectangle of its 8 projected corners.  A tile whose
+// pixel rectangle misses that rectangle (with a margin) has no ray that
+// reaches a cell: its pixels are 0 and it need not be marched.
+struct Footprint {
+    double u_lo, u_hi, w_lo, w_hi;
+};
+
+static Footprint footprint(const RayView &rv) {
+    Footprint f{INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int c = 0; c < 8; c++) {
+        double d[3];
+        for (int a = 0; a < 3; a++)
+            d[a] = ((c >> a) & 1 ? rv.st.n[a] * rv.st.cell[a] : 0.0) - rv.centre[a];
+        const double u = d[0] * rv.eu[0] + d[1] * rv.eu[1] + d[2] * rv.eu[2];
+        const double w = d[0] * rv.ev[0] + d[1] * rv.ev[1] + d[2] * rv.ev[2];
+        f.u_lo = std::min(f.u_lo, u);
+        f.u_hi = std::max(f.u_hi, u);
+        f.w_lo = std::min(f.w_lo, w);
+        f.w_hi = std::max(f.w_hi, w);
+    }
+    // a pixel's width plus a relative margin: rounding never drops a tile
+    // that a ray of it could reach
+    const double m = rv.ps + 1e-9 * std::max({fabs(f.u_lo), fabs(f.u_hi), fabs(f.w_lo),
+                                             fabs(f.w_hi), 1.0});
+    f.u_lo -= m; f.u_hi += m; f.w_lo -= m; f.w_hi += m;
+    return f;
+}
+
+static bool tile_misses_grid(const RayView &rv, const Footprint &f, int tx, int ty, int tw,
+                             int th) {
+    const double u0 = (tx * tw + 0.5 - 0.5 * rv.width) * rv.ps;
+    const double u1 = ((tx + 1) * tw - 0.5 - 0.5 * rv.width) * rv.ps;
+    const double w0 = (ty * th + 0.5 - 0.5 * rv.height) * rv.ps;
+    const double w1 = ((ty + 1) * th - 0.5 - 0.5 * rv.height) * rv.ps;
+    return u1 < f.u_lo || u0 > f.u_hi || w1 < f.w_lo || w0 > f.w_hi;
+}
+
 static double tile_cost(const RayView &rv, int tx, int ty, int tw, int th) {
     const double u = ((tx + 0.5) * tw - 0.5 * rv.width) * rv.ps;
     const double w = ((ty + 0.5) * th - 0.5 * rv.height) * rv.ps;
@@ -1050,13 +1089,21 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             return fail(DART_E_INVAL,
                         "view %d: %dx%d image in %dx%d tiles needs more than 65536 tiles per "
                         "side", i, rv.width, rv.height, tw, th);
+        // (labelled stacks: the first sub-domain's box is not the domain's)
+        const bool skip = rv.n_blocks == 0;
+        const Footprint fp = footprint(rv);
         for (int ty = 0; ty < nty; ty++)
             for (int tx = 0; tx < ntx; tx++) {
                 Tile t;
                 t.view = vi;
                 t.tx = (uint16_t)tx;
                 t.ty = (uint16_t)ty;
-                g.tiles.push_back(t);
+                if (skip && tile_misses_grid(rv, fp, tx, ty, tw, th)) {
+                    // cleared by a fill kernel; an adding view keeps its values
+                    if (!(rv.flags & F_ACCUMULATE)) g.clear.push_back(t);
+                } else {
+                    g.tiles.push_back(t);
+                }
             }
     }
     for (Group &g : groups) {
@@ -1166,6 +1213,10 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         if (!bounds_set)
             for (size_t q = 0; q <= nq; q++)
                 g.q_begin[q] = (uint32_t)(((uint64_t)g.tiles.size() * q) / nq);
+        // the tiles to clear follow the queued ones in the same array
+        g.n_clear = (uint32_t)g.clear.size();
+        g.tiles.insert(g.tiles.end(), g.clear.begin(), g.clear.end());
+        g.clear.clear();
     }
     return DART_OK;
 }
@@ -1182,10 +1233,15 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
     const int blocks = std::max(1, cus * tun.waves_per_cu / 4);
     for (size_t gi = 0; gi < groups.size(); gi++) {
         const Group &g = groups[gi];
+        if (g.n_clear > 0) {
+            e = launch_clear_tiles(dviews + g.view_off, dtiles + g.tile_off + g.q_begin[g.n_queues],
+                                   g.n_clear, stream);
+            if (e != hipSuccess) return e;
+        }
         BatchLaunch bl;
         bl.views = dviews + g.view_off;
         bl.tiles = dtiles + g.tile_off;
-        bl.n_tiles = (uint32_t)g.tiles.size();
+        bl.n_tiles = (uint32_t)g.q_begin[g.n_queues];
         bl.head = (uint32_t *)(acc + 2 * (size_t)n + 4 * gi);
         bl.n_queues = g.n_queues;
         for (uint32_t q = 0; q <= g.n_queues; q++) bl.q_begin[q] = g.q_begin[q];

@@ -177,3 +177,51 @@ def test_count_bytes(env):
                   f"lines {lb} vs {rlb}", flush=True)
     finally:
         d.dart_free_epochs(st)
+
+
+def test_batched_writes_every_pixel(env, keep_tuning):
+    """Tiles whose rays all miss the grid are not marched: a fill kernel
+    writes their zeros.  Images prefilled with NaN must come out equal, bit for
+    bit, to the plain kernel's (which writes every pixel), for FP32 and FP64
+    images; an adding view (DART_ACCUMULATE) keeps its prior values there."""
+    d, torch = env
+    dims = (40, 48, 56)
+    j, b, times = synth.jet_torch(dims, 3, 21, gamma_spine=3.0, n_knots=1)
+    torch.cuda.synchronize()
+    jh, bh = j.cpu().numpy(), b.cpu().numpy()
+    s32 = d.dart_load_epochs(dims, (1, 1, 1), times, j, b, d.DART_F32)
+    s64 = d.dart_load_epochs(dims, (1, 1, 1), times, jh.astype(np.float64), bh.astype(np.float64),
+                             d.DART_F64)
+    L = synth.diag(dims)
+    try:
+        for tile in ((64, 1, 0), (16, 4, 6), (8, 8, 0)):
+            d.dart_set_tuning(tile[0], tile[1], 8, 4, 1, tile[2], 8)
+            for st, dt, npdt in ((s32, d.DART_F32, np.float32), (s64, d.DART_F64, np.float64)):
+                # images twice the grid's extent: most tiles miss it
+                views = [d.View(th, ph, 100, 72, 2.0 * L / 100, 1.0, 0.6, 0, dt)
+                         for th, ph in ((20.0, 10.0), (75.0, 240.0))]
+                tdt = torch.float32 if npdt == np.float32 else torch.float64
+                got = [torch.full((v.height, v.width), float("nan"), dtype=tdt, device="cuda")
+                       for v in views]
+                ref = [torch.zeros((v.height, v.width), dtype=tdt, device="cuda") for v in views]
+                d.dart_render_batch([st] * 2, views, got)
+                for v, im in zip(views, ref):
+                    d.dart_render(st, v, im)
+                torch.cuda.synchronize()
+                for a, r in zip(got, ref):
+                    an, rn = a.cpu().numpy(), r.cpu().numpy()
+                    assert not np.isnan(an).any(), f"unwritten pixels, tile {tile}"
+                    assert np.array_equal(an, rn), f"tile {tile}"
+                    assert (rn == 0).mean() > 0.3      # the views are mostly sky
+        # adding views keep their values where no ray reaches the grid
+        d.dart_set_tuning(16, 4, 8, 4, 1, 0, 8)
+        views = [d.View(30.0, 50.0, 100, 72, 2.0 * L / 100, 1.0, 0.6, d.DART_ACCUMULATE)]
+        got = [torch.full((72, 100), 1.5, dtype=torch.float32, device="cuda")]
+        ref = [torch.full((72, 100), 1.5, dtype=torch.float32, device="cuda")]
+        d.dart_render_batch([s32], views, got)
+        d.dart_render(s32, views[0], ref[0])
+        torch.cuda.synchronize()
+        assert np.array_equal(got[0].cpu().numpy(), ref[0].cpu().numpy())
+    finally:
+        d.dart_free_epochs(s32)
+        d.dart_free_epochs(s64)
