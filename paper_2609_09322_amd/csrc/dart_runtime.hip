@@ -987,42 +987,74 @@ static bool orient_flips(const RayView &rv, const dart_tuning &tun) {
 }
 
 // Rays of a view are parallel: the pixel ray at image-plane coordinates (u, w)
-// can meet the grid box only if (u, w) lies in the box's projection, which is
-// inside the bounding rectangle of its 8 projected corners.  A tile whose
-// pixel rectangle misses that rectangle (with a margin) has no ray that
-// reaches a cell: its pixels are 0 and it need not be marched.
+// can meet the grid box only if (u, w) lies in the box's projection, the
+// convex hull of its 8 projected corners, whose edges are projections of box
+// edges.  A tile's pixel rectangle (widened by a pixel) that a separating axis
+// keeps apart from that hull has no ray that reaches a cell: its pixels are 0
+// and it need not be marched.  The axes tried are u, w and the normals of the
+// 12 projected box edges (every hull edge among them; the others are valid
+// axes too), so the test is exact up to the margin.
 struct Footprint {
-    double u_lo, u_hi, w_lo, w_hi;
+    double u[8], w[8];             // projected corners
+    double nu[14], nw[14];         // candidate axes
+    double lo[14], hi[14];         // the hull's extent along each
+    int n_axes;
+    double margin;
 };
 
 static Footprint footprint(const RayView &rv) {
-    Footprint f{INFINITY, -INFINITY, INFINITY, -INFINITY};
+    Footprint f;
     for (int c = 0; c < 8; c++) {
         double d[3];
         for (int a = 0; a < 3; a++)
             d[a] = ((c >> a) & 1 ? rv.st.n[a] * rv.st.cell[a] : 0.0) - rv.centre[a];
-        const double u = d[0] * rv.eu[0] + d[1] * rv.eu[1] + d[2] * rv.eu[2];
-        const double w = d[0] * rv.ev[0] + d[1] * rv.ev[1] + d[2] * rv.ev[2];
-        f.u_lo = std::min(f.u_lo, u);
-        f.u_hi = std::max(f.u_hi, u);
-        f.w_lo = std::min(f.w_lo, w);
-        f.w_hi = std::max(f.w_hi, w);
+        f.u[c] = d[0] * rv.eu[0] + d[1] * rv.eu[1] + d[2] * rv.eu[2];
+        f.w[c] = d[0] * rv.ev[0] + d[1] * rv.ev[1] + d[2] * rv.ev[2];
     }
+    double scale = 1.0;
+    for (int c = 0; c < 8; c++) scale = std::max({scale, fabs(f.u[c]), fabs(f.w[c])});
     // a pixel's width plus a relative margin: rounding never drops a tile
     // that a ray of it could reach
-    const double m = rv.ps + 1e-9 * std::max({fabs(f.u_lo), fabs(f.u_hi), fabs(f.w_lo),
-                                             fabs(f.w_hi), 1.0});
-    f.u_lo -= m; f.u_hi += m; f.w_lo -= m; f.w_hi += m;
+    f.margin = rv.ps + 1e-9 * scale;
+    f.n_axes = 0;
+    auto add_axis = [&f](double nu, double nw) {
+        const double len = std::sqrt(nu * nu + nw * nw);
+        if (!(len > 1e-12)) return;  // an edge seen end-on
+        nu /= len;
+        nw /= len;
+        double lo = INFINITY, hi = -INFINITY;
+        for (int c = 0; c < 8; c++) {
+            const double x = nu * f.u[c] + nw * f.w[c];
+            lo = std::min(lo, x);
+            hi = std::max(hi, x);
+        }
+        const int k = f.n_axes++;
+        f.nu[k] = nu; f.nw[k] = nw; f.lo[k] = lo; f.hi[k] = hi;
+    };
+    add_axis(1.0, 0.0);
+    add_axis(0.0, 1.0);
+    for (int c = 0; c < 8; c++)
+        for (int a = 0; a < 3; a++)
+            if (!((c >> a) & 1)) {
+                const int e = c | (1 << a);  // the box edge from corner c along axis a
+                add_axis(-(f.w[e] - f.w[c]), f.u[e] - f.u[c]);
+            }
     return f;
 }
 
 static bool tile_misses_grid(const RayView &rv, const Footprint &f, int tx, int ty, int tw,
                              int th) {
-    const double u0 = (tx * tw + 0.5 - 0.5 * rv.width) * rv.ps;
-    const double u1 = ((tx + 1) * tw - 0.5 - 0.5 * rv.width) * rv.ps;
-    const double w0 = (ty * th + 0.5 - 0.5 * rv.height) * rv.ps;
-    const double w1 = ((ty + 1) * th - 0.5 - 0.5 * rv.height) * rv.ps;
-    return u1 < f.u_lo || u0 > f.u_hi || w1 < f.w_lo || w0 > f.w_hi;
+    const double u0 = (tx * tw + 0.5 - 0.5 * rv.width) * rv.ps - f.margin;
+    const double u1 = ((tx + 1) * tw - 0.5 - 0.5 * rv.width) * rv.ps + f.margin;
+    const double w0 = (ty * th + 0.5 - 0.5 * rv.height) * rv.ps - f.margin;
+    const double w1 = ((ty + 1) * th - 0.5 - 0.5 * rv.height) * rv.ps + f.margin;
+    for (int k = 0; k < f.n_axes; k++) {
+        // the rectangle's extent along the axis: its corners' projections
+        const double a = f.nu[k] * u0, b = f.nu[k] * u1, c = f.nw[k] * w0, d = f.nw[k] * w1;
+        const double lo = std::min(a, b) + std::min(c, d), hi = std::max(a, b) + std::max(c, d);
+        if (hi < f.lo[k] || lo > f.hi[k]) return true;
+    }
+    return false;
 }
 
 static double tile_cost(const RayView &rv, int tx, int ty, int tw, int th) {

@@ -198,13 +198,17 @@ def test_batched_writes_every_pixel(env, keep_tuning):
             d.dart_set_tuning(tile[0], tile[1], 8, 4, 1, tile[2], 8)
             for st, dt, npdt in ((s32, d.DART_F32, np.float32), (s64, d.DART_F64, np.float64)):
                 # images twice the grid's extent: most tiles miss it
+                # (axis-aligned views see edges end-on; the others cut corners
+                # off the projection's bounding rectangle)
                 views = [d.View(th, ph, 100, 72, 2.0 * L / 100, 1.0, 0.6, 0, dt)
-                         for th, ph in ((20.0, 10.0), (75.0, 240.0))]
+                         for th, ph in ((20.0, 10.0), (75.0, 240.0), (0.0, 0.0), (90.0, 0.0),
+                                        (90.0, 90.0), (54.7, 45.0), (123.0, 301.0),
+                                        (170.0, 77.0))]
                 tdt = torch.float32 if npdt == np.float32 else torch.float64
                 got = [torch.full((v.height, v.width), float("nan"), dtype=tdt, device="cuda")
                        for v in views]
                 ref = [torch.zeros((v.height, v.width), dtype=tdt, device="cuda") for v in views]
-                d.dart_render_batch([st] * 2, views, got)
+                d.dart_render_batch([st] * len(views), views, got)
                 for v, im in zip(views, ref):
                     d.dart_render(st, v, im)
                 torch.cuda.synchronize()
