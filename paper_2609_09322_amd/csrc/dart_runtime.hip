@@ -988,73 +988,90 @@ static bool orient_flips(const RayView &rv, const dart_tuning &tun) {
 
 // Rays of a view are parallel: the pixel ray at image-plane coordinates (u, w)
 // can meet the grid box only if (u, w) lies in the box's projection, the
-// convex hull of its 8 projected corners, whose edges are projections of box
-// edges.  A tile's pixel rectangle (widened by a pixel) that a separating axis
-// keeps apart from that hull has no ray that reaches a cell: its pixels are 0
-// and it need not be marched.  The axes tried are u, w and the normals of the
-// 12 projected box edges (every hull edge among them; the others are valid
-// axes too), so the test is exact up to the margin.
+// convex hull of its 8 projected corners.  A row of tiles covers a band of w;
+// the hull's part in that band spans an interval of u, found on the hull's
+// edges (a convex region reaches its extremes on its boundary).  A tile whose
+// u-interval misses it, both widened by a pixel, has no ray that reaches a
+// cell: its pixels are 0 and it need not be marched.  Per view the planner
+// builds the hull once and per row clips its edges to the band, so the test
+// costs a few compares per tile (the server plans every wave).
 struct Footprint {
-    double u[8], w[8];             // projected corners
-    double nu[14], nw[14];         // candidate axes
-    double lo[14], hi[14];         // the hull's extent along each
-    int n_axes;
+    std::vector<std::pair<double, double>> hull;  // (u, w), counter-clockwise
     double margin;
 };
 
 static Footprint footprint(const RayView &rv) {
     Footprint f;
+    std::vector<std::pair<double, double>> pts(8);
+    double scale = 1.0;
     for (int c = 0; c < 8; c++) {
         double d[3];
         for (int a = 0; a < 3; a++)
             d[a] = ((c >> a) & 1 ? rv.st.n[a] * rv.st.cell[a] : 0.0) - rv.centre[a];
-        f.u[c] = d[0] * rv.eu[0] + d[1] * rv.eu[1] + d[2] * rv.eu[2];
-        f.w[c] = d[0] * rv.ev[0] + d[1] * rv.ev[1] + d[2] * rv.ev[2];
+        pts[c].first = d[0] * rv.eu[0] + d[1] * rv.eu[1] + d[2] * rv.eu[2];
+        pts[c].second = d[0] * rv.ev[0] + d[1] * rv.ev[1] + d[2] * rv.ev[2];
+        scale = std::max({scale, fabs(pts[c].first), fabs(pts[c].second)});
     }
-    double scale = 1.0;
-    for (int c = 0; c < 8; c++) scale = std::max({scale, fabs(f.u[c]), fabs(f.w[c])});
     // a pixel's width plus a relative margin: rounding never drops a tile
     // that a ray of it could reach
     f.margin = rv.ps + 1e-9 * scale;
-    f.n_axes = 0;
-    auto add_axis = [&f](double nu, double nw) {
-        const double len = std::sqrt(nu * nu + nw * nw);
-        if (!(len > 1e-12)) return;  // an edge seen end-on
-        nu /= len;
-        nw /= len;
-        double lo = INFINITY, hi = -INFINITY;
-        for (int c = 0; c < 8; c++) {
-            const double x = nu * f.u[c] + nw * f.w[c];
-            lo = std::min(lo, x);
-            hi = std::max(hi, x);
-        }
-        const int k = f.n_axes++;
-        f.nu[k] = nu; f.nw[k] = nw; f.lo[k] = lo; f.hi[k] = hi;
+    // convex hull (monotone chain)
+    std::sort(pts.begin(), pts.end());
+    auto cross = [](const std::pair<double, double> &o, const std::pair<double, double> &p,
+                    const std::pair<double, double> &q) {
+        return (p.first - o.first) * (q.second - o.second) -
+               (p.second - o.second) * (q.first - o.first);
     };
-    add_axis(1.0, 0.0);
-    add_axis(0.0, 1.0);
-    for (int c = 0; c < 8; c++)
-        for (int a = 0; a < 3; a++)
-            if (!((c >> a) & 1)) {
-                const int e = c | (1 << a);  // the box edge from corner c along axis a
-                add_axis(-(f.w[e] - f.w[c]), f.u[e] - f.u[c]);
-            }
+    std::vector<std::pair<double, double>> h(16);
+    int k = 0;
+    for (int i = 0; i < 8; i++) {
+        while (k >= 2 && cross(h[k - 2], h[k - 1], pts[i]) <= 0) k--;
+        h[k++] = pts[i];
+    }
+    for (int i = 6, t = k + 1; i >= 0; i--) {
+        while (k >= t && cross(h[k - 2], h[k - 1], pts[i]) <= 0) k--;
+        h[k++] = pts[i];
+    }
+    h.resize(k > 1 ? k - 1 : k);
+    f.hull = h;
     return f;
 }
 
-static bool tile_misses_grid(const RayView &rv, const Footprint &f, int tx, int ty, int tw,
-                             int th) {
-    const double u0 = (tx * tw + 0.5 - 0.5 * rv.width) * rv.ps - f.margin;
-    const double u1 = ((tx + 1) * tw - 0.5 - 0.5 * rv.width) * rv.ps + f.margin;
-    const double w0 = (ty * th + 0.5 - 0.5 * rv.height) * rv.ps - f.margin;
-    const double w1 = ((ty + 1) * th - 0.5 - 0.5 * rv.height) * rv.ps + f.margin;
-    for (int k = 0; k < f.n_axes; k++) {
-        // the rectangle's extent along the axis: its corners' projections
-        const double a = f.nu[k] * u0, b = f.nu[k] * u1, c = f.nw[k] * w0, d = f.nw[k] * w1;
-        const double lo = std::min(a, b) + std::min(c, d), hi = std::max(a, b) + std::max(c, d);
-        if (hi < f.lo[k] || lo > f.hi[k]) return true;
+// The u-interval of the hull's part with w in [w0, w1] (widened by the
+// margin); false when that part is empty.
+static bool band_span(const Footprint &f, double w0, double w1, double *u_lo, double *u_hi) {
+    w0 -= f.margin;
+    w1 += f.margin;
+    double lo = INFINITY, hi = -INFINITY;
+    const size_t n = f.hull.size();
+    if (n < 3) {  // degenerate: keep the tiles
+        *u_lo = -INFINITY;
+        *u_hi = INFINITY;
+        return true;
     }
-    return false;
+    for (size_t i = 0; i < n; i++) {
+        const auto &p = f.hull[i], &q = f.hull[(i + 1) % n];
+        // the part of edge p -> q with w in [w0, w1]
+        double ta = 0.0, tb = 1.0;
+        const double dw = q.second - p.second;
+        if (dw == 0.0) {
+            if (p.second < w0 || p.second > w1) continue;
+        } else {
+            double t0 = (w0 - p.second) / dw, t1 = (w1 - p.second) / dw;
+            if (t0 > t1) std::swap(t0, t1);
+            ta = std::max(ta, t0);
+            tb = std::min(tb, t1);
+            if (ta > tb) continue;
+        }
+        const double ua = p.first + ta * (q.first - p.first);
+        const double ub = p.first + tb * (q.first - p.first);
+        lo = std::min({lo, ua, ub});
+        hi = std::max({hi, ua, ub});
+    }
+    if (!(lo <= hi)) return false;
+    *u_lo = lo - f.margin;
+    *u_hi = hi + f.margin;
+    return true;
 }
 
 static double tile_cost(const RayView &rv, int tx, int ty, int tw, int th) {
@@ -1124,19 +1141,29 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         // (labelled stacks: the first sub-domain's box is not the domain's)
         const bool skip = rv.n_blocks == 0;
         const Footprint fp = footprint(rv);
-        for (int ty = 0; ty < nty; ty++)
+        for (int ty = 0; ty < nty; ty++) {
+            double u_lo = -INFINITY, u_hi = INFINITY;
+            bool row_hits = true;
+            if (skip) {
+                const double w0 = (ty * th + 0.5 - 0.5 * rv.height) * rv.ps;
+                const double w1 = ((ty + 1) * th - 0.5 - 0.5 * rv.height) * rv.ps;
+                row_hits = band_span(fp, w0, w1, &u_lo, &u_hi);
+            }
             for (int tx = 0; tx < ntx; tx++) {
                 Tile t;
                 t.view = vi;
                 t.tx = (uint16_t)tx;
                 t.ty = (uint16_t)ty;
-                if (skip && tile_misses_grid(rv, fp, tx, ty, tw, th)) {
+                const double u0 = (tx * tw + 0.5 - 0.5 * rv.width) * rv.ps;
+                const double u1 = ((tx + 1) * tw - 0.5 - 0.5 * rv.width) * rv.ps;
+                if (skip && (!row_hits || u1 < u_lo || u0 > u_hi)) {
                     // cleared by a fill kernel; an adding view keeps its values
                     if (!(rv.flags & F_ACCUMULATE)) g.clear.push_back(t);
                 } else {
                     g.tiles.push_back(t);
                 }
             }
+        }
     }
     for (Group &g : groups) {
         const size_t nq = MAX_QUEUES;

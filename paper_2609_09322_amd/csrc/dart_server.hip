@@ -273,7 +273,13 @@ static void launch_wave(dart_server *srv, std::unique_lock<std::mutex> &lk, int 
         views[i].flags |= DART_DEVICE_PTRS;
         imgs[i] = (char *)srv->dev_base + r->dev_off;
     }
-    const dart_tuning tun = tuning_for(stacks[0]);
+    dart_tuning tun = tuning_for(stacks[0]);
+    // Every wave is planned here, on the scheduler thread, while the other
+    // streams render.  Orders 1 and 4 estimate every tile's ray length and
+    // sort by it (at saturation, tens of ms of host time per wave of
+    // hundreds of requests, more than the wave's device time); waves keep the
+    // tuned shape with tiles in row order instead.
+    if (tun.order == 1 || tun.order == 4) tun.order = 0;
     std::vector<Group> groups;
     dart_status st = plan_batch(stacks.data(), views.data(), n, imgs.data(), tun, groups);
     if (st != DART_OK) {
