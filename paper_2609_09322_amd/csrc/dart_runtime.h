@@ -49,7 +49,10 @@ struct dart_stack {
     // at the first render after the records change, when memory allows
     void *jplane = nullptr;
     uint64_t jplane_bytes = 0;
-    uint64_t jplane_gen = 0;            // the generation it was packed from (0: never)
+    // the generation it was packed from (0: never); read without the lock by
+    // planners on other threads, so published after the pack has completed
+    std::atomic<uint64_t> jplane_gen{0};
+    uint64_t jplane_no_room = 0;        // a generation for which hipMalloc failed
     bool vector() const { return !comps.empty(); }
     int channels() const { return comps.empty() ? 1 : (int)comps.size(); }
 };

@@ -922,14 +922,16 @@ static bool jplane_eligible(const dart_stack *s) {
 }
 
 bool dart::jplane_ready(const dart_stack *s) {
-    return jplane_eligible(s) && s->jplane && s->jplane_gen == s->generation;
+    return jplane_eligible(s) && s->jplane_gen.load(std::memory_order_acquire) == s->generation;
 }
 
 dart_status dart::refresh_jplane(const dart_stack *cs, hipStream_t stream, bool may_alloc) {
     if (!jplane_eligible(cs)) return DART_OK;
     dart_stack *s = const_cast<dart_stack *>(cs);
     std::lock_guard<std::mutex> g(s->mu);
-    if (s->jplane && s->jplane_gen == s->generation) return DART_OK;
+    if (s->jplane_gen.load(std::memory_order_relaxed) == s->generation) return DART_OK;
+    // (no second attempt to allocate for records that have not changed)
+    if (s->jplane_no_room == s->generation) return DART_OK;
     for (char f : s->filled)
         if (!f) return DART_OK;  // (such a stack is not rendered)
     // nothing is packed into a graph the caller is capturing: its renders read
@@ -942,6 +944,7 @@ dart_status dart::refresh_jplane(const dart_stack *cs, hipStream_t stream, bool 
     if (s->jplane_bytes != need && !may_alloc) return DART_OK;
     // renders still reading the old plane must finish first
     for (auto &u : s->uses) HIP_TRY(hipEventSynchronize(u.second), "wait for renders");
+    s->jplane_gen.store(0, std::memory_order_release);
     if (s->jplane_bytes != need) {
         if (s->jplane) (void)hipFree(s->jplane);
         s->jplane = nullptr;
@@ -949,6 +952,7 @@ dart_status dart::refresh_jplane(const dart_stack *cs, hipStream_t stream, bool 
         void *p = nullptr;
         if (hipMalloc(&p, need) != hipSuccess) {
             (void)hipGetLastError();  // no room: renders read whole records
+            s->jplane_no_room = s->generation;
             return DART_OK;
         }
         s->jplane = p;
@@ -958,7 +962,7 @@ dart_status dart::refresh_jplane(const dart_stack *cs, hipStream_t stream, bool 
             "pack emissivity plane");
     // complete before a render on any stream reads it
     HIP_TRY(hipStreamSynchronize(stream), "sync");
-    s->jplane_gen = s->generation;
+    s->jplane_gen.store(s->generation, std::memory_order_release);
     return DART_OK;
 }
 
