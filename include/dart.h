@@ -68,7 +68,8 @@ typedef enum { DART_F64 = 0, DART_F32 = 1, DART_F16 = 2, DART_BF16 = 3 } dart_dt
 #define DART_NO_LOOKBACK 0x1u   /* routine B: tbar = t_obs for every cell (Eq. 3, Eq. 10) */
 #define DART_NO_BEAMING 0x2u    /* routine A: D = 1 */
 #define DART_NEAREST_EPOCH 0x4u /* weight 1 on the epoch closest to tbar (ties: earlier) */
-#define DART_NO_KAHAN 0x8u      /* plain (uncompensated) FP32 accumulation */
+#define DART_NO_KAHAN 0x8u      /* plain (uncompensated) FP32 accumulation (such views read
+                                   whole records, not the emissivity plane) */
 #define DART_FORCE_F64_DDA 0x10u /* FP64 ray parameters (DDA crossings, retarded times) for
                                     16-bit stacks too; FP64 and FP32 stacks always use them,
                                     16-bit stacks when a ray may cross more than 4096 cells */
@@ -86,6 +87,10 @@ typedef enum { DART_F64 = 0, DART_F32 = 1, DART_F16 = 2, DART_BF16 = 3 } dart_dt
 #define DART_RECORDS_ONLY 0x200u /* view: read the whole record of every cell instead of the
                                    stack's emissivity plane (see dart_stack_get_info); the
                                    image is the same bit for bit: for comparisons */
+#define DART_PLANE_ADDR64 0x400u /* view: address the emissivity plane through 64-bit
+                                   pointers, as planes over 4 GiB always are, instead of the
+                                   32-bit offsets used for smaller ones; the image is the same
+                                   bit for bit: for comparisons */
 #define DART_ACCUMULATE 0x80u   /* view: add the render to the values already in the image
                                    instead of overwriting them, so partial renders of
                                    sub-domains sum into one buffer (Sec. 4, Fig. 5; Sec. 6.2).
@@ -145,7 +150,10 @@ dart_status dart_free_epochs(dart_stack *s);
  * jet's volume at rest is then read at a quarter of the bytes.  Images, flux
  * and cell-steps are bit for bit those of whole-record reads
  * (DART_RECORDS_ONLY).  Without room for the plane (hipMalloc fails) renders
- * read whole records.  FP64, labelled, vector and streamed stacks have none. */
+ * read whole records, as do views with DART_NO_KAHAN.  Planes of at most 4 GiB
+ * are read through 32-bit offsets, larger ones through 64-bit addresses
+ * (DART_PLANE_ADDR64 asks for those on any plane).  FP64, labelled, vector and
+ * streamed stacks have none. */
 typedef struct {
     int32_t dims[3];
     int32_t n_epochs;
@@ -395,8 +403,8 @@ dart_status dart_count_lines(const dart_stack *s, const dart_view *v, uint64_t *
 /* The same counts as renders read the stack: with the emissivity plane (packed
  * first if it is missing or stale), each sample of positive weight costs one
  * plane value (a quarter of a record) and, when its record carries the
- * read-whole mark, the record as well; without it (DART_RECORDS_ONLY, or no
- * plane) a record.  compulsory_out: those bytes; line_bytes_out: the distinct
+ * read-whole mark, the record as well; without it (DART_RECORDS_ONLY,
+ * DART_NO_KAHAN, or no plane) a record.  compulsory_out: those bytes; line_bytes_out: the distinct
  * 128-byte lines of the plane and of the records that hold them, times 128.
  * The image bytes are not included.  Either output may be NULL.  Untimed
  * instrumentation, as above. */

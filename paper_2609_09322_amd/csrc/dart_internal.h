@@ -16,6 +16,7 @@ enum : uint32_t {
     F_DEVICE_PTRS = 0x20u,
     F_ACCUMULATE = 0x80u,
     F_EXACT = 0x100u,
+    F_PLANE32 = 0x1000u,  // the view's emissivity plane is read through 32-bit offsets
 };
 
 // Resident stack as the kernels see it.  Records (j, bx, by, bz) are stored
@@ -105,7 +106,10 @@ hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *
 // labelled stacks (block loop), 4 exact temporal integration, 8 eight cells per
 // batch (else four), 16 vector stacks (only alone: no other bit but 8), 32 the
 // views' stacks have an emissivity plane (not with 2 or 16).
-enum : int { KV_SYNC = 1, KV_LABELLED = 2, KV_EXACT = 4, KV_K8 = 8, KV_VEC = 16, KV_JP = 32 };
+enum : int {
+    KV_SYNC = 1, KV_LABELLED = 2, KV_EXACT = 4, KV_K8 = 8, KV_VEC = 16, KV_JP = 32,
+    KV_JP32 = 64,  // with KV_JP: the plane through 32-bit byte offsets (F_PLANE32)
+};
 hipError_t launch_batch(int store, bool f64_dda, int variant, const BatchLaunch &bl,
                         int grid_blocks, hipStream_t s);
 // Marks the samples of positive weight of a render of v (moving_only: only

@@ -226,13 +226,13 @@ struct Ray {
 // is the low L bits of its offset, (lz << (a+b)) | (ly << a) | lx, so the test
 // reads the offset itself.  All rays of a view step the same way along each
 // axis, so these increments and tests are uniform over a wavefront: the walk
-// updates the offset with an and, a compare, two selects and an add, without
-// multiplies.
+// updates the offset with an and, a compare and a select per axis, two selects
+// of the stepping axis and an add, without multiplies.
 struct OffsetSteps {
     uint32_t field[3];   // bits of lx, ly, lz in the offset
     uint32_t last[3];    // their value in the last cell of a brick along the step
     uint32_t inner[3];   // offset change of a step inside a brick
-    uint32_t extra[3];   // added to it for a step across a brick face
+    uint32_t cross[3];   // offset change of a step across a brick face
 };
 
 __device__ __forceinline__ OffsetSteps offset_steps(const StackDev &st, const RayView &v) {
@@ -249,13 +249,13 @@ __device__ __forceinline__ OffsetSteps offset_steps(const StackDev &st, const Ra
         o.field[q] = ((1u << lb[q]) - 1u) * in_[q];
         o.last[q] = down ? 0u : o.field[q];
         // (unsigned negation: a step down subtracts modulo 2^32)
-        o.inner[q] = down ? 0u - in_[q] : in_[q];
-        const uint32_t extra = down ? 0u - k[q] : k[q];
-        // Held in a vector register for the whole walk: the per-step select
-        // reads its condition from a scalar register pair, and an instruction
-        // takes at most one scalar operand, so a scalar `extra` would be
-        // copied to a vector register at every step.
-        asm("v_mov_b32 %0, %1" : "=v"(o.extra[q]) : "s"(extra));
+        const uint32_t inner = down ? 0u - in_[q] : in_[q];
+        const uint32_t cross = inner + (down ? 0u - k[q] : k[q]);
+        // Both held in vector registers for the whole walk: the per-step
+        // select between them reads its condition from a scalar register
+        // pair, and an instruction takes at most one scalar operand.
+        asm("v_mov_b32 %0, %1" : "=v"(o.inner[q]) : "s"(inner));
+        asm("v_mov_b32 %0, %1" : "=v"(o.cross[q]) : "s"(cross));
     }
     return o;
 }
@@ -342,6 +342,17 @@ __device__ __forceinline__ bool ray_setup(const RayView &v, const StackDev &st,
     return r.entry < r.stop;
 }
 
+// max(a, b) of two walk positions (never NaN).  FP32: one v_max_f32 (fmaxf
+// would first quiet both operands); FP64: a compare and select.  (Equal
+// operands give the same value either way, up to the sign of a zero, which no
+// use of the entry distinguishes.)
+__device__ __forceinline__ float later_of(float a, float b) {
+    float m;
+    asm("v_max_f32 %0, %1, %2" : "=v"(m) : "v"(a), "v"(b));
+    return m;
+}
+__device__ __forceinline__ double later_of(double a, double b) { return a > b ? a : b; }
+
 // The axis of the next crossing (ties: x before y before z); exit is
 // min(sa0, sa1, sa2), the current cell's exit.
 template <typename R>
@@ -362,23 +373,24 @@ __device__ __forceinline__ void step_axis(const Ray<R> &r, const R exit, bool &a
 // below stop; a cell entered on a tie with it has no chord.
 template <typename R>
 __device__ __forceinline__ bool ray_advance(const OffsetSteps &os, Ray<R> &r, const R exit) {
-    bool ax, ay, az;
-    step_axis(r, exit, ax, ay, az);
-    // brick face ahead along each axis, from the current cell's offset (each
-    // select takes one uniform operand and zero, so no uniform value is copied
-    // to a vector register first)
-    const uint32_t dx = os.inner[0] + ((r.off & os.field[0]) == os.last[0] ? os.extra[0] : 0u);
-    const uint32_t dy = os.inner[1] + ((r.off & os.field[1]) == os.last[1] ? os.extra[1] : 0u);
-    const uint32_t dz = os.inner[2] + ((r.off & os.field[2]) == os.last[2] ? os.extra[2] : 0u);
-    r.off += ax ? dx : (ay ? dy : dz);
+    // (bitwise, not short-circuit, logic: every select below is evaluated on
+    // every lane, with no branch)
+    const bool ax = r.sa0 == exit;
+    const bool ey = r.sa1 == exit;
+    const bool ay = ey & !ax, az = !(ax | ey);
+    // brick face ahead along each axis, from the current cell's offset
+    const uint32_t dx = (r.off & os.field[0]) == os.last[0] ? os.cross[0] : os.inner[0];
+    const uint32_t dy = (r.off & os.field[1]) == os.last[1] ? os.cross[1] : os.inner[1];
+    const uint32_t dz = (r.off & os.field[2]) == os.last[2] ? os.cross[2] : os.inner[2];
+    const uint32_t dyz = ey ? dy : dz;
+    r.off += ax ? dx : dyz;
     r.c0 += ax ? (R)1 : (R)0;
     r.c1 += ay ? (R)1 : (R)0;
     r.c2 += az ? (R)1 : (R)0;
     r.sa0 = fma(r.c0, r.d0, r.b0);
     r.sa1 = fma(r.c1, r.d1, r.b1);
     r.sa2 = fma(r.c2, r.d2, r.b2);
-    // (a compare and select, not fmax: no canonicalisation of the operands)
-    r.entry = exit > r.entry ? exit : r.entry;
+    r.entry = later_of(exit, r.entry);
     return r.entry < r.stop;
 }
 
@@ -547,6 +559,26 @@ __device__ __forceinline__ void mark_ray(const RayView &v, int pi, int pj, uint3
     }
 }
 
+// Adds term to the compensated sum (sum, comp) (Kahan); a zero term leaves
+// both as they are, so cells not taken in a batch do not perturb the sum.
+// Without compensation (kahan false) comp stays 0, and the same steps are a
+// plain add.  (The sum starts at +0 and never becomes -0, so skipping a zero
+// term is the same as adding it.)
+// The steps are never fused with the product that made the term, and the
+// test stays a branch (an empty volatile asm keeps the compiler from turning
+// it into selects, which would cost two more vector instructions per term).
+template <typename A>
+__device__ __forceinline__ void kahan_add(A &sum, A &comp, A term, bool kahan) {
+#pragma clang fp contract(off)
+    if (term != (A)0) {
+        asm volatile("");
+        const A yk = term - comp;
+        const A tk = sum + yk;
+        comp = kahan ? (tk - sum) - yk : (A)0;
+        sum = tk;
+    }
+}
+
 // Cells walked per batch (K): a lane walks K cells of its ray, then issues all
 // their record loads back to back, then consumes them.  The batched kernel
 // comes with K = 4 and K = 8 (a tuning choice); the plain kernel uses 4.
@@ -624,7 +656,12 @@ __device__ __forceinline__ bool in_window(double s, double lo, double hi) {
 // 2K records at once and consumes them after a single wait: many gathers per
 // lane in flight instead of one dependent load per step.  (K is 4 or 8 in the
 // batched kernel, CELLS_PER_BATCH in the plain one.)
-template <int S, typename R, int SYNC, bool EX, int K, bool VEC, bool SINGLE, bool JP>
+//
+// JP: 0 whole records; 1 the emissivity plane through 64-bit addresses; 2 the
+// plane through 32-bit byte offsets from its start (planes of at most 4 GiB):
+// a cell's offset is one add and a shift, and the elements of its two epochs
+// are loaded at that offset from two wavefront-uniform bases.
+template <int S, typename R, int SYNC, bool EX, int K, bool VEC, bool SINGLE, int JP>
 __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &st,
                                              const double *centre, int pi, int pj, bool in_image,
                                              const ldsdouble *tab, uint32_t &nsteps,
@@ -638,8 +675,13 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     static_assert(!(JP && (VEC || S == ST_F64)), "no emissivity plane for these stacks");
     // The walk addresses elements of the emissivity plane (JP) or records:
     // both have the record index space, so one offset serves either.
-    using E = typename std::conditional<JP, JF, Raw>::type;
+    using E = typename std::conditional<JP != 0, JF, Raw>::type;
     using GE = const E __attribute__((address_space(1)));
+    constexpr bool O32 = JP == 2;
+    constexpr uint32_t ESH = sizeof(JF) == 2 ? 1u : 2u;  // log2 of the element size
+    using GB = const uint8_t __attribute__((address_space(1)));
+    // a cell's element: its address, or (O32) its byte offset in the plane
+    using Addr = typename std::conditional<O32, uint32_t, GE *>::type;
     constexpr int NX = VEC ? 3 : 1;  // extra component slots
     if constexpr (VEC) {
 #pragma unroll
@@ -652,7 +694,8 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     const bool beaming = !(v.flags & F_NO_BEAMING);
     const int M = st.n_epochs;
     constexpr bool single = SINGLE;
-    const bool kahan = !(v.flags & F_NO_KAHAN);
+    // (views without compensation are never given the emissivity plane)
+    const bool kahan = JP != 0 || !(v.flags & F_NO_KAHAN);
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
     const R gap = (R)v.sync_gap;
     GRaw *gdata = (GRaw *)st.data;
@@ -664,8 +707,18 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     Bracket<R> br;
     bracket_init(v, st, lookback, br, tab);
     const OffsetSteps os = offset_steps(st, v);
-    GE *ebase = wdata + (int64_t)br.m * estride;  // elements of epoch br.m
+    // elements of epoch br.m: their address, or (O32) the index of the first
+    Addr abase;
+    if constexpr (O32) abase = 0u;
+    else abase = wdata;
+    Addr ebase = abase + (int64_t)br.m * estride;
     int ebase_m = br.m;
+    // (O32) the two epochs' loads: one byte offset from two bases
+    GB *pb0 = (GB *)wdata, *pb1 = pb0 + second * (int64_t)sizeof(E);
+    auto cell_addr = [&](Addr e) -> Addr {
+        if constexpr (O32) return (e + r.off) << ESH;
+        else return e + r.off;
+    };
     A sum = 0, comp = 0;
     A xsum[NX], xcomp[NX];
 #pragma unroll
@@ -693,11 +746,11 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
         } else if (!alive) {
             break;
         }
-        GE *addr[K];
+        Addr addr[K];
         A cds[K], cw[K];  // chord and weight, already in the accumulation type
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            addr[k] = wdata;  // a valid address for cells not taken in this batch
+            addr[k] = abase;  // a valid element for cells not taken in this batch
             cds[k] = (A)0;
             cw[k] = (A)0;
             if (alive) {
@@ -723,10 +776,10 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                     const bool contrib = ds > (R)0;
                     const R wt = (br.am - mid) * br.inv_dt;
                     if (br.m != ebase_m) {
-                        ebase = wdata + (int64_t)br.m * estride;
+                        ebase = abase + (int64_t)br.m * estride;
                         ebase_m = br.m;
                     }
-                    addr[k] = ebase + r.off;
+                    addr[k] = cell_addr(ebase);
                     cds[k] = contrib ? (A)ds : (A)0;
                     cw[k] = (A)wt;
                     count += (contrib && !cell_counted) ? 1u : 0u;
@@ -745,10 +798,10 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                     const bool contrib = ds > (R)0 && in_window(mid, r_lo, r_hi);
                     R wt = (R)v.fixed_w;
                     if (lookback) {
-                        bracket_seek(v, st, mid, br, tab, ebase, wdata, estride);
+                        bracket_seek(v, st, mid, br, tab, ebase, abase, estride);
                         wt = (br.am - mid) * br.inv_dt;
                     }
-                    GE *e0 = ebase;
+                    Addr e0 = ebase;
                     if constexpr (single) {
                         if (M >= 2) {
                             const bool later =
@@ -757,7 +810,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                         }
                         wt = (R)0;
                     }
-                    addr[k] = e0 + r.off;
+                    addr[k] = cell_addr(e0);
                     cds[k] = contrib ? (A)ds : (A)0;
                     cw[k] = (A)wt;
                     count += contrib ? 1u : 0u;
@@ -779,8 +832,13 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
             JF q0[K], q1[K];
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                q0[k] = addr[k][0];
-                q1[k] = addr[k][second];
+                if constexpr (O32) {
+                    q0[k] = *(GJ *)(pb0 + addr[k]);
+                    q1[k] = *(GJ *)(pb1 + addr[k]);
+                } else {
+                    q0[k] = addr[k][0];
+                    q1[k] = addr[k][second];
+                }
             }
             uint32_t any_bits = 0u;
 #pragma unroll
@@ -792,21 +850,16 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                     const A b1 = (A)decode_j<S>(q1[k]);
                     val = val + cw[k] * (b1 - val);
                     const A term = cds[k] * val;
-                    if (kahan && term != (A)0) {
-                        const A yk = term - comp;
-                        const A tk = sum + yk;
-                        comp = (tk - sum) - yk;
-                        sum = tk;
-                    } else {
-                        sum += term;
-                    }
+                    kahan_add(sum, comp, term, kahan);
                 }
                 continue;
             }
             // the same cells' whole records, then the record path
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                GRaw *ra = gdata + (addr[k] - wdata);
+                GRaw *ra;
+                if constexpr (O32) ra = gdata + (addr[k] >> ESH);
+                else ra = gdata + (addr[k] - wdata);
                 r0[k] = load_grec<S>(ra);
                 r1[k] = load_grec<S>(ra + second);
             }
@@ -857,14 +910,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                 const A b1 = (A)record_j<S>(r1[k]);
                 val = val + cw[k] * (b1 - val);
                 const A term = cds[k] * val;
-                if (kahan && term != (A)0) {
-                    const A yk = term - comp;
-                    const A tk = sum + yk;
-                    comp = (tk - sum) - yk;
-                    sum = tk;
-                } else {
-                    sum += term;
-                }
+                kahan_add(sum, comp, term, kahan);
             }
             continue;
         }
@@ -891,28 +937,14 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                         const A xb = (A)(decode_j<S>(j1[k][c]) * f1);
                         xv = xv + cw[k] * (xb - xv);
                         const A xt = cds[k] * xv;
-                        if (kahan && xt != (A)0) {
-                            const A yk = xt - xcomp[c];
-                            const A tk = xsum[c] + yk;
-                            xcomp[c] = (tk - xsum[c]) - yk;
-                            xsum[c] = tk;
-                        } else {
-                            xsum[c] += xt;
-                        }
+                        kahan_add(xsum[c], xcomp[c], xt, kahan);
                     }
                 }
             }
             const A term = cds[k] * val;
             // a zero term leaves the compensated sum as it is, so cells not
             // taken in a batch do not perturb it (rounding of sum - comp)
-            if (kahan && term != (A)0) {
-                const A yk = term - comp;
-                const A tk = sum + yk;
-                comp = (tk - sum) - yk;
-                sum = tk;
-            } else {
-                sum += term;
-            }
+            kahan_add(sum, comp, term, kahan);
         }
     }
     nsteps += count;
@@ -923,7 +955,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     return (double)sum - (double)comp;
 }
 
-template <int S, typename R, int SYNC, bool EX, int K, bool VEC = false, bool JP = false>
+template <int S, typename R, int SYNC, bool EX, int K, bool VEC = false, int JP = 0>
 __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
                                         const double *centre, int pi, int pj, bool in_image,
                                         const ldsdouble *tab, uint32_t &nsteps,
@@ -942,7 +974,7 @@ __device__ __forceinline__ double march(const RayView &v, const StackDev &st,
 // is uniform over the wavefront, as the depth-synchronous mode needs.
 // Vector stacks (VEC, never with LAB) also return components 1.. in ext.
 template <int S, typename R, int SYNC, bool LAB, bool EX, int K, bool VEC = false,
-          bool JP = false>
+          int JP = 0>
 __device__ __forceinline__ double pixel_value(const RayView &v, int pi, int pj, bool in_image,
                                               const ldsdouble *tab, uint32_t &nsteps,
                                               double *ext = nullptr) {
@@ -994,7 +1026,7 @@ __device__ __forceinline__ void store_pixel(const RayView &v, int pi, int pj, do
 // ------------------------------------------------------------------ kernels
 
 // Plain kernel: one thread per pixel in row order, one launch per image.
-template <int S, typename R, bool LAB, bool EX, bool VEC = false, bool JP = false>
+template <int S, typename R, bool LAB, bool EX, bool VEC = false, int JP = 0>
 __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
                                                unsigned long long *step_acc) {
     __shared__ double s_tab[4][2 * EPOCH_TAB_MAX];
@@ -1031,7 +1063,7 @@ __global__ void __launch_bounds__(256) k_plain(RayView v, double *flux_acc,
 // round-robin workgroup dispatch is the chunk of its own XCD, and moves on to
 // the other chunks when its own runs dry.
 template <int S, typename R, int SYNC, bool LAB, bool EX, int K, bool VEC = false,
-          bool JP = false>
+          int JP = 0>
 __global__ void __launch_bounds__(256) k_batch(BatchLaunch bl,
                                                const RayView *__restrict__ views,
                                                const Tile *__restrict__ tiles) {
@@ -1301,8 +1333,13 @@ static hipError_t plain_impl(const RayView &v, double *flux_acc, unsigned long l
     if constexpr (S != ST_F64) {
         // (the planner gives an emissivity plane only to plain stacks)
         if (v.st.jplane && !lab && v.n_chan == 1) {
-            if (ex) hipLaunchKernelGGL((k_plain<S, R, false, true, false, true>), g, b, 0, s, v, flux_acc, step_acc);
-            else hipLaunchKernelGGL((k_plain<S, R, false, false, false, true>), g, b, 0, s, v, flux_acc, step_acc);
+            if (v.flags & F_PLANE32) {
+                if (ex) hipLaunchKernelGGL((k_plain<S, R, false, true, false, 2>), g, b, 0, s, v, flux_acc, step_acc);
+                else hipLaunchKernelGGL((k_plain<S, R, false, false, false, 2>), g, b, 0, s, v, flux_acc, step_acc);
+            } else {
+                if (ex) hipLaunchKernelGGL((k_plain<S, R, false, true, false, 1>), g, b, 0, s, v, flux_acc, step_acc);
+                else hipLaunchKernelGGL((k_plain<S, R, false, false, false, 1>), g, b, 0, s, v, flux_acc, step_acc);
+            }
             return hipGetLastError();
         }
     }
@@ -1329,7 +1366,7 @@ hipError_t launch_plain(const RayView &v, double *flux_acc, unsigned long long *
     return hipErrorInvalidValue;
 }
 
-template <int S, typename R, int SYNC, bool LAB, bool EX, bool JP = false>
+template <int S, typename R, int SYNC, bool LAB, bool EX, int JP = 0>
 static void batch_launch_k(const BatchLaunch &bl, bool k8, int grid_blocks, hipStream_t s) {
     const dim3 g((unsigned)grid_blocks), b(256);
     if (k8)
@@ -1356,12 +1393,22 @@ static hipError_t batch_impl(const BatchLaunch &bl, int variant, int grid_blocks
         return hipGetLastError();
     }
     if constexpr (S != ST_F64) {
+        if ((variant & KV_JP) && (variant & KV_JP32)) {
+            switch (variant & 7) {
+                case 0: batch_launch_k<S, R, 0, false, false, 2>(bl, k8, grid_blocks, s); break;
+                case 1: batch_launch_k<S, R, 1, false, false, 2>(bl, k8, grid_blocks, s); break;
+                case 4: batch_launch_k<S, R, 0, false, true, 2>(bl, k8, grid_blocks, s); break;
+                case 5: batch_launch_k<S, R, 1, false, true, 2>(bl, k8, grid_blocks, s); break;
+                default: return hipErrorInvalidValue;  // (labelled stacks read whole records)
+            }
+            return hipGetLastError();
+        }
         if (variant & KV_JP) {
             switch (variant & 7) {
-                case 0: batch_launch_k<S, R, 0, false, false, true>(bl, k8, grid_blocks, s); break;
-                case 1: batch_launch_k<S, R, 1, false, false, true>(bl, k8, grid_blocks, s); break;
-                case 4: batch_launch_k<S, R, 0, false, true, true>(bl, k8, grid_blocks, s); break;
-                case 5: batch_launch_k<S, R, 1, false, true, true>(bl, k8, grid_blocks, s); break;
+                case 0: batch_launch_k<S, R, 0, false, false, 1>(bl, k8, grid_blocks, s); break;
+                case 1: batch_launch_k<S, R, 1, false, false, 1>(bl, k8, grid_blocks, s); break;
+                case 4: batch_launch_k<S, R, 0, false, true, 1>(bl, k8, grid_blocks, s); break;
+                case 5: batch_launch_k<S, R, 1, false, true, 1>(bl, k8, grid_blocks, s); break;
                 default: return hipErrorInvalidValue;  // (labelled stacks read whole records)
             }
             return hipGetLastError();

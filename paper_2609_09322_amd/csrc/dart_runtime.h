@@ -84,6 +84,7 @@ struct Group {
     bool vec = false;       // views of vector stacks
     bool exact = false;     // views with exact temporal integration
     bool jp = false;        // views that read their stacks' emissivity planes
+    bool jp32 = false;      // ... through 32-bit offsets (planes of at most 4 GiB)
     std::vector<RayView> views;
     // queued tiles [0, q_begin[n_queues]), then n_clear tiles whose rays all
     // miss the grid (their pixels are set to 0 by a fill kernel)

@@ -666,7 +666,8 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
         return fail(DART_E_INVAL, "FP64 images need an FP64 stack");
     if (v->flags & ~(uint32_t)(DART_NO_LOOKBACK | DART_NO_BEAMING | DART_NEAREST_EPOCH |
                                DART_NO_KAHAN | DART_FORCE_F64_DDA | DART_DEVICE_PTRS |
-                               DART_ACCUMULATE | DART_EXACT_TIME | DART_RECORDS_ONLY))
+                               DART_ACCUMULATE | DART_EXACT_TIME | DART_RECORDS_ONLY |
+                               DART_PLANE_ADDR64))
         return fail(DART_E_INVAL, "unknown view flags 0x%x", v->flags);
     if ((v->flags & DART_EXACT_TIME) && (v->flags & DART_NEAREST_EPOCH))
         return fail(DART_E_INVAL, "DART_EXACT_TIME integrates the linear interpolation; "
@@ -715,7 +716,14 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
     rv->height = v->height;
     rv->out_f64 = v->out_dtype == DART_F64;
     rv->st = s->dev;
-    rv->st.jplane = (!(v->flags & DART_RECORDS_ONLY) && jplane_ready(s)) ? s->jplane : nullptr;
+    // (the plane kernels always compensate their sums: views without
+    // compensation read whole records)
+    rv->st.jplane = (!(v->flags & (DART_RECORDS_ONLY | DART_NO_KAHAN)) && jplane_ready(s))
+                        ? s->jplane
+                        : nullptr;
+    // a plane of at most 4 GiB is read through 32-bit byte offsets
+    if (rv->st.jplane && s->jplane_bytes <= (1ull << 32) && !(v->flags & DART_PLANE_ADDR64))
+        rv->flags |= F_PLANE32;
     rv->blocks = s->dev_blocks;
     rv->n_blocks = (int32_t)s->parts.size();
     rv->n_chan = s->channels();
@@ -1113,7 +1121,8 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
         if (!images[i]) return fail(DART_E_INVAL, "images[%d] is NULL", i);
         rv.image = images[i];
         rv.acc_index = i;
-        const int key = (rv.st.jplane ? 64 : 0) + rv.st.store * 16 + (rv.n_chan > 1 ? 8 : 0) +
+        const int key = ((rv.flags & F_PLANE32) ? 128 : 0) + (rv.st.jplane ? 64 : 0) +
+                        rv.st.store * 16 + (rv.n_chan > 1 ? 8 : 0) +
                         ((rv.flags & F_F64_DDA) ? 4 : 0) + (rv.n_blocks > 0 ? 2 : 0) +
                         ((rv.flags & F_EXACT) ? 1 : 0);
         auto it = gindex.find(key);
@@ -1126,6 +1135,7 @@ dart_status dart::plan_batch(const dart_stack *const *stacks, const dart_view *v
             groups.back().exact = (rv.flags & F_EXACT) != 0;
             groups.back().vec = rv.n_chan > 1;
             groups.back().jp = rv.st.jplane != nullptr;
+            groups.back().jp32 = (rv.flags & F_PLANE32) != 0;
         }
         Group &g = groups[it->second];
         const uint32_t vi = (uint32_t)g.views.size();
@@ -1313,7 +1323,7 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
         const int variant = g.vec ? (KV_VEC | (tun.cells_per_batch == 8 ? KV_K8 : 0))
                                   : (tun.depth_sync > 0 ? KV_SYNC : 0) |
                                         (g.labelled ? KV_LABELLED : 0) | (g.exact ? KV_EXACT : 0) |
-                                        (g.jp ? KV_JP : 0) |
+                                        (g.jp ? KV_JP : 0) | (g.jp32 ? KV_JP32 : 0) |
                                         (tun.cells_per_batch == 8 ? KV_K8 : 0);
         e = launch_batch(g.store, g.f64, variant, bl, blocks, stream);
         if (e != hipSuccess) return e;
@@ -1758,7 +1768,7 @@ extern "C" dart_status dart_count_bytes(const dart_stack *s, const dart_view *v,
         while ((elem << (l + 1)) <= 128u) l++;
         return l;
     };
-    const bool plane = !(v->flags & DART_RECORDS_ONLY) && jplane_ready(s);
+    const bool plane = !(v->flags & (DART_RECORDS_ONLY | DART_NO_KAHAN)) && jplane_ready(s);
     uint64_t samples = 0, lines = 0;
     st = count_marked(s, v, -1, false, &samples, hip_stream);
     if (st == DART_OK && line_bytes_out)

@@ -30,6 +30,7 @@ DART_KERNEL_PLAIN = 0x40
 DART_ACCUMULATE = 0x80
 DART_EXACT_TIME = 0x100
 DART_RECORDS_ONLY = 0x200
+DART_PLANE_ADDR64 = 0x400
 
 EXPORTS = ["dart_load_epochs", "dart_stack_create", "dart_stack_set_epochs", "dart_free_epochs",
            "dart_stack_get_info", "dart_stack_read_epoch", "dart_stack_rebrick", "dart_stack_set_placement",

@@ -6,7 +6,9 @@ The two are the same computation of Eq. 19 on the same stored values, so the
 images and cell-steps must agree bit for bit; flux totals are FP64 atomics
 whose order varies, so they agree to 1e-12.  Cases: FP32, FP16 and BF16
 stacks; the batched kernel with and without depth synchronisation, four and
-eight cells per batch and exact temporal integration; the plain kernel; a
+eight cells per batch and exact temporal integration; the plain kernel; the
+plane read through 32-bit offsets (planes up to 4 GiB, the default here) and
+through 64-bit addresses (DART_PLANE_ADDR64, the form of larger planes); a
 stack with negative and -0 emissivity and -0 velocity components (records
 the plane must send to the whole-record path), checked against the FP64
 oracle as well; a refill of some epochs (the plane is packed again); and the
@@ -103,6 +105,15 @@ def test_plane_equals_records(env, keep_tuning, storage):
         ex = _views(d, d.DART_EXACT_TIME)
         _assert_same(_render_pair(d, torch, st, ex), f"{storage} exact time")
         _assert_same(_render_pair(d, torch, st, views[:2], batched=False), f"{storage} plain")
+        # the plane through 64-bit addresses
+        wide = _views(d, d.DART_PLANE_ADDR64)
+        for sync, k in ((0, 4), (6, 8)):
+            d.dart_set_tuning(16, 4, 12, 4, 1, sync, k)
+            _assert_same(_render_pair(d, torch, st, wide), f"{storage} 64-bit sync {sync} k {k}")
+        wex = _views(d, d.DART_EXACT_TIME | d.DART_PLANE_ADDR64)
+        _assert_same(_render_pair(d, torch, st, wex), f"{storage} 64-bit exact time")
+        _assert_same(_render_pair(d, torch, st, wide[:2], batched=False), f"{storage} 64-bit plain")
+        print(f"{storage} 64-bit plane addresses: identical", flush=True)
         # the plane is a quarter of the record bytes
         after = _plane_bytes(d, st)
         assert after - before == before // 4, (before, after)
