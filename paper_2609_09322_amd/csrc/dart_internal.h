@@ -64,6 +64,7 @@ struct RayView {
     int32_t width, height;
     int32_t fixed_m;        // NO_LOOKBACK: epoch bracket at t_obs (-1: t_obs outside coverage)
     double fixed_w;         // NO_LOOKBACK: weight of epoch fixed_m + 1
+    float fixed_wf;         // the same rounded to FP32 (read as such by FP32 walks)
     double sync_gap;        // batched kernel: depth-synchronous horizon (length), 0 = off
     void *image;            // [height][width] float or double (device)
     int32_t out_f64;

@@ -159,6 +159,23 @@ __device__ __forceinline__ typename RecT<S>::val decode_j(typename JFieldT<S>::r
     else return __uint_as_float((uint32_t)w << 16);
 }
 
+// decode_j(b) - decode_j(a) in FP32, of two loaded plane elements (16-bit
+// elements as their bits zero-extended to 32, as the load leaves them).  FP16:
+// one mixed-precision fma, b * 1 - a with both operands converted exactly and
+// one rounding: the same value as the difference of the converted elements,
+// without the two conversions.
+template <int S, typename Q>
+__device__ __forceinline__ float plane_diff(Q a, Q b) {
+    using JF = typename JFieldT<S>::raw;
+    if constexpr (S == ST_F16) {
+        float d;
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[1,0,1]" : "=v"(d) : "v"(b), "v"(a));
+        return d;
+    } else {
+        return (float)decode_j<S>((JF)b) - (float)decode_j<S>((JF)a);
+    }
+}
+
 // Emissivity plane (StackDev::jplane): one element per record, j alone in the
 // storage type, with its sign bit standing for "read the whole record": set
 // when the velocity bits are not all zero or j itself has its sign bit set
@@ -456,17 +473,39 @@ __device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &s
     }
 }
 
-// The same, keeping `base` (the records of epoch b.m) in step with the bracket.
+// The walk's bracket in doubled units, for mid2 = entry + exit (twice the
+// chord midpoint): thr2 = 2 a_m, or +inf at m = 0 where the bracket cannot
+// move (one compare per cell instead of two); am2 = 2 a_m, am1_2 = 2 a_{m+1},
+// hdt = inv_dt / 2.  Doubling and halving are exact, so every test on mid2 and
+// the weight (am2 - mid2) hdt equal those on the midpoint itself, and the walk
+// saves the halving of every midpoint.
+template <typename R>
+struct Doubled {
+    R thr2, am2, am1_2, hdt;
+};
+template <typename R>
+__device__ __forceinline__ void doubled_of(const Bracket<R> &b, Doubled<R> &d) {
+    d.am2 = (R)2 * b.am;
+    d.am1_2 = (R)2 * b.am1;
+    d.hdt = (R)0.5 * b.inv_dt;
+    d.thr2 = b.m > 0 ? d.am2 : (R)INFINITY;
+}
+
+// bracket_seek for mid = mid2 / 2, keeping d and `base` (the elements of epoch
+// b.m) in step with the bracket.
 template <typename R, typename P>
-__device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &st, R mid,
-                                             Bracket<R> &b, const ldsdouble *tab, P &base,
-                                             P data, int64_t estride) {
-    while (b.m > 0 && mid > b.am) {
-        b.m--;
-        b.am1 = b.am;
-        b.am = epoch_a<R>(v, st, tab, b.m);
-        b.inv_dt = epoch_inv_dt<R>(st, tab, b.m);
+__device__ __forceinline__ void bracket_seek2(const RayView &v, const StackDev &st, R mid2,
+                                              Bracket<R> &b, Doubled<R> &d, const ldsdouble *tab,
+                                              P &base, P data, int64_t estride) {
+    if (mid2 > d.thr2) {
+        do {
+            b.m--;
+            b.am1 = b.am;
+            b.am = epoch_a<R>(v, st, tab, b.m);
+            b.inv_dt = epoch_inv_dt<R>(st, tab, b.m);
+        } while (b.m > 0 && mid2 > (R)2 * b.am);
         base = data + (int64_t)b.m * estride;
+        doubled_of(b, d);
     }
 }
 
@@ -697,6 +736,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     // (views without compensation are never given the emissivity plane)
     const bool kahan = JP != 0 || !(v.flags & F_NO_KAHAN);
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
+    const R lo2 = (R)2 * r_lo, hi2 = (R)2 * r_hi;  // the window for mid2 (exact)
     const R gap = (R)v.sync_gap;
     GRaw *gdata = (GRaw *)st.data;
     GE *wdata = JP ? (GE *)st.jplane : (GE *)st.data;
@@ -706,6 +746,8 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     const int64_t second = single ? 0 : estride;
     Bracket<R> br;
     bracket_init(v, st, lookback, br, tab);
+    Doubled<R> dbl;
+    doubled_of(br, dbl);
     const OffsetSteps os = offset_steps(st, v);
     // elements of epoch br.m: their address, or (O32) the index of the first
     Addr abase;
@@ -733,6 +775,12 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     int guard = (st.n[0] + st.n[1] + st.n[2] + (EX ? M + 3 : 1)) * (SYNC != 0 ? 64 : 1);
     R piece = -(R)INFINITY;  // EX: start of the part of the current cell not yet taken
     bool cell_counted = false;
+    // Weights of the batch's cells.  A cell not taken keeps the weight of an
+    // earlier batch (finite, and multiplied by a zero chord), so no default
+    // is written per cell.
+    A cw[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) cw[k] = (A)0;
 
     for (;;) {
         if (--guard < 0) break;
@@ -747,12 +795,11 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
             break;
         }
         Addr addr[K];
-        A cds[K], cw[K];  // chord and weight, already in the accumulation type
+        A cds[K];  // chord, already in the accumulation type
 #pragma unroll
         for (int k = 0; k < K; k++) {
             addr[k] = abase;  // a valid element for cells not taken in this batch
             cds[k] = (A)0;
-            cw[k] = (A)0;
             if (alive) {
                 const R entry = r.entry;
                 const R exit = fmin(r.sa0, fmin(r.sa1, r.sa2));
@@ -794,18 +841,20 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                 } else if (!EX && (SYNC == 0 || entry < lim)) {
                     // (the rearmost ray has entry == front < lim, so each batch
                     // takes at least one cell or ends a ray)
-                    const R ds = exit - entry, mid = (R)0.5 * (entry + exit);
-                    const bool contrib = ds > (R)0 && in_window(mid, r_lo, r_hi);
-                    R wt = (R)v.fixed_w;
+                    const R ds = exit - entry, mid2 = entry + exit;
+                    const bool contrib = ds > (R)0 && in_window(mid2, lo2, hi2);
+                    // (FP32 walks read the weight stored in FP32: no conversion
+                    // per cell)
+                    R wt = std::is_same<R, float>::value ? (R)v.fixed_wf : (R)v.fixed_w;
                     if (lookback) {
-                        bracket_seek(v, st, mid, br, tab, ebase, abase, estride);
-                        wt = (br.am - mid) * br.inv_dt;
+                        bracket_seek2(v, st, mid2, br, dbl, tab, ebase, abase, estride);
+                        wt = (dbl.am2 - mid2) * dbl.hdt;
                     }
                     Addr e0 = ebase;
                     if constexpr (single) {
                         if (M >= 2) {
                             const bool later =
-                                lookback ? (mid - br.am1) < (br.am - mid) : wt > (R)0.5;
+                                lookback ? (mid2 - dbl.am1_2) < (dbl.am2 - mid2) : wt > (R)0.5;
                             if (later) e0 = ebase + estride;
                         }
                         wt = (R)0;
@@ -829,26 +878,28 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
             // (Marks on cells that contribute nothing send the batch to the
             // whole records too, which is never wrong, and saves a test per
             // cell.)
-            JF q0[K], q1[K];
+            // (16-bit elements held zero-extended, as loaded)
+            using QJ = typename std::conditional<sizeof(JF) == 2, uint32_t, JF>::type;
+            QJ q0[K], q1[K];
 #pragma unroll
             for (int k = 0; k < K; k++) {
                 if constexpr (O32) {
-                    q0[k] = *(GJ *)(pb0 + addr[k]);
-                    q1[k] = *(GJ *)(pb1 + addr[k]);
+                    q0[k] = (QJ) * (GJ *)(pb0 + addr[k]);
+                    q1[k] = (QJ) * (GJ *)(pb1 + addr[k]);
                 } else {
-                    q0[k] = addr[k][0];
-                    q1[k] = addr[k][second];
+                    q0[k] = (QJ)addr[k][0];
+                    q1[k] = (QJ)addr[k][second];
                 }
             }
             uint32_t any_bits = 0u;
 #pragma unroll
-            for (int k = 0; k < K; k++) any_bits |= jplane_bits<S>(q0[k]) | jplane_bits<S>(q1[k]);
+            for (int k = 0; k < K; k++)
+                any_bits |= jplane_bits<S>((JF)q0[k]) | jplane_bits<S>((JF)q1[k]);
             if (!__any(jplane_mark<S>(any_bits) != 0u)) {
 #pragma unroll
                 for (int k = 0; k < K; k++) {
-                    A val = (A)decode_j<S>(q0[k]);
-                    const A b1 = (A)decode_j<S>(q1[k]);
-                    val = val + cw[k] * (b1 - val);
+                    const A val =
+                        (A)decode_j<S>((JF)q0[k]) + cw[k] * plane_diff<S>(q0[k], q1[k]);
                     const A term = cds[k] * val;
                     kahan_add(sum, comp, term, kahan);
                 }

@@ -741,12 +741,15 @@ dart_status dart::resolve_view(const dart_stack *s, const dart_view *v, RayView 
             rv->fixed_w = M >= 2 ? (v->t_obs - t[m]) / (t[m + 1] - t[m]) : 0.0;
         } else {
             rv->fixed_m = -1;
+            rv->fixed_w = 0.0;
         }
     } else {
         rv->s_lo = v->t_obs - t[M - 1];
         rv->s_hi = v->t_obs - t[0];
         rv->fixed_m = 0;
+        rv->fixed_w = 0.0;
     }
+    rv->fixed_wf = (float)rv->fixed_w;
     return DART_OK;
 }
 
