@@ -623,35 +623,32 @@ __device__ __forceinline__ void kahan_add(A &sum, A &comp, A term, bool kahan) {
 // comes with K = 4 and K = 8 (a tuning choice); the plain kernel uses 4.
 constexpr int CELLS_PER_BATCH = 4;
 
-// Minimum over the 64 lanes of a wavefront (every lane active): within each
-// row of 16 lanes by DPP lane permutations (swap neighbours, swap pairs, mirror
-// the half row, mirror the row), then across the four rows from one lane of
-// each.  No LDS round trips.  The operands are entries of the walk (never NaN),
-// so a compare and select stands in for fminf, which would first quiet its
-// operands; every source lane of these permutations lies in its own row and is
-// active, so the DPP moves need no old value.
-__device__ __forceinline__ float min_sel(float a, float b) { return b < a ? b : a; }
-__device__ __forceinline__ float dpp_min_row(float x) {
-    // DPP controls: quad_perm [1,0,3,2] = 0xb1, quad_perm [2,3,0,1] = 0x4e,
-    // row_half_mirror = 0x141, row_mirror = 0x140
-    x = min_sel(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf,
-                                                              0xf, true)));
-    x = min_sel(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4e, 0xf,
-                                                              0xf, true)));
-    x = min_sel(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xf,
-                                                              0xf, true)));
-    x = min_sel(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xf,
-                                                              0xf, true)));
-    return x;
-}
+// Minimum over the 64 lanes of a wavefront (every lane active), in six
+// instructions that each take the minimum of a lane's value and a DPP-moved
+// one: within each row of 16 lanes (swap neighbours, swap pairs, mirror the
+// half row, mirror the row: every lane then holds its row's minimum), then the
+// last lane of row 0 into row 1 and of row 2 into row 3 (row_bcast:15), then
+// the last lane of row 1 into rows 2 and 3 (row_bcast:31): lane 63 holds the
+// wavefront's minimum.  No LDS round trips.  The operands are entries of the
+// walk (never NaN), so v_min_f32 needs no quieting of its operands; every
+// source lane of these moves is active.  Each move reads a register the
+// previous instruction wrote, which takes two wait states (s_nop 1).
 __device__ __forceinline__ float wave_min(float x) {
-    x = dpp_min_row(x);
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
-    // (on scalar operands fminf is cheaper: one min of three)
-    return fminf(fminf(r0, r1), fminf(r2, r3));
+    asm("s_nop 1\n\t"
+        "v_min_f32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_min_f32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_min_f32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_min_f32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_min_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_min_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "s_nop 1"
+        : "+v"(x));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 __device__ __forceinline__ double wave_min(double x) {
 #pragma unroll
