@@ -473,6 +473,21 @@ __device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &s
     }
 }
 
+// The same, keeping `base` (the elements of epoch b.m) in step with the
+// bracket.
+template <typename R, typename P>
+__device__ __forceinline__ void bracket_seek(const RayView &v, const StackDev &st, R mid,
+                                             Bracket<R> &b, const ldsdouble *tab, P &base,
+                                             P data, int64_t estride) {
+    while (b.m > 0 && mid > b.am) {
+        b.m--;
+        b.am1 = b.am;
+        b.am = epoch_a<R>(v, st, tab, b.m);
+        b.inv_dt = epoch_inv_dt<R>(st, tab, b.m);
+        base = data + (int64_t)b.m * estride;
+    }
+}
+
 // The walk's bracket in doubled units, for mid2 = entry + exit (twice the
 // chord midpoint): thr2 = 2 a_m, or +inf at m = 0 where the bracket cannot
 // move (one compare per cell instead of two); am2 = 2 a_m, am1_2 = 2 a_{m+1},
@@ -733,6 +748,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
     // (views without compensation are never given the emissivity plane)
     const bool kahan = JP != 0 || !(v.flags & F_NO_KAHAN);
     const R r_lo = (R)v.s_lo, r_hi = (R)v.s_hi;
+    constexpr bool DOUBLED = std::is_same<R, float>::value || JP != 0;
     const R lo2 = (R)2 * r_lo, hi2 = (R)2 * r_hi;  // the window for mid2 (exact)
     const R gap = (R)v.sync_gap;
     GRaw *gdata = (GRaw *)st.data;
@@ -838,20 +854,35 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                 } else if (!EX && (SYNC == 0 || entry < lim)) {
                     // (the rearmost ray has entry == front < lim, so each batch
                     // takes at least one cell or ends a ray)
-                    const R ds = exit - entry, mid2 = entry + exit;
-                    const bool contrib = ds > (R)0 && in_window(mid2, lo2, hi2);
+                    // The midpoint is kept doubled (one compare for the
+                    // bracket, no halving), except by FP64 rays over whole
+                    // records: there the doubled form made the compiler's
+                    // schedule hold twice the registers (290 against 146)
+                    const R ds = exit - entry;
+                    const R mid2 = entry + exit, mid = (R)0.5 * mid2;
+                    const bool contrib = ds > (R)0 && (DOUBLED ? in_window(mid2, lo2, hi2)
+                                                                 : in_window(mid, r_lo, r_hi));
                     // (FP32 walks read the weight stored in FP32: no conversion
                     // per cell)
                     R wt = std::is_same<R, float>::value ? (R)v.fixed_wf : (R)v.fixed_w;
                     if (lookback) {
-                        bracket_seek2(v, st, mid2, br, dbl, tab, ebase, abase, estride);
-                        wt = (dbl.am2 - mid2) * dbl.hdt;
+                        if constexpr (DOUBLED) {
+                            bracket_seek2(v, st, mid2, br, dbl, tab, ebase, abase, estride);
+                            wt = (dbl.am2 - mid2) * dbl.hdt;
+                        } else {
+                            bracket_seek(v, st, mid, br, tab, ebase, abase, estride);
+                            wt = (br.am - mid) * br.inv_dt;
+                        }
                     }
                     Addr e0 = ebase;
                     if constexpr (single) {
                         if (M >= 2) {
-                            const bool later =
-                                lookback ? (mid2 - dbl.am1_2) < (dbl.am2 - mid2) : wt > (R)0.5;
+                            bool later;
+                            if constexpr (DOUBLED)
+                                later = lookback ? (mid2 - dbl.am1_2) < (dbl.am2 - mid2)
+                                                 : wt > (R)0.5;
+                            else
+                                later = lookback ? (mid - br.am1) < (br.am - mid) : wt > (R)0.5;
                             if (later) e0 = ebase + estride;
                         }
                         wt = (R)0;

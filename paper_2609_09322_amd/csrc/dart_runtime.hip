@@ -1579,7 +1579,8 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
         dart_status r = dart_render_batch(stacks, vv.data(), n, imgs.data(), nullptr, nullptr, hip_stream);
         if (r != DART_OK) return r;
         // best of several replays: about 40 ms of timing per candidate, at
-        // least 2 and at most 12 replays (short batches are noisier)
+        // least 2 and at most 48 replays (short batches are noisier: a
+        // sub-millisecond batch gets dozens)
         float ms_min = INFINITY;
         int reps = 2;
         for (int rep = 0; rep < reps; rep++) {
@@ -1591,7 +1592,7 @@ extern "C" dart_status dart_autotune(dart_stack *const *stacks, const dart_view 
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e0, e1);
             ms_min = std::min(ms_min, ms);
-            if (rep == 0) reps = std::max(2, std::min(12, (int)(40.0f / std::max(ms, 1e-3f))));
+            if (rep == 0) reps = std::max(2, std::min(48, (int)(40.0f / std::max(ms, 1e-3f))));
         }
         *ms_out = ms_min;
         return DART_OK;
