@@ -136,9 +136,13 @@ __device__ __forceinline__ typename RecT<S>::val boost_factor(const typename Rec
 // which near the beaming peak (1 + beta.s ~ 0.05 at Lorentz factor 4) is a
 // systematic ~1e-6 relative error of D^p over the whole image.  (The factor is
 // exactly 1 without beaming or at rest, and j * 1 is j.)
+// (The product is rounded on its own, never fused into the interpolation that
+// uses it, so every path that meets a sample, from the emissivity plane or
+// from whole records, gives it the same bits.)
 template <int S>
 __device__ __forceinline__ typename RecT<S>::val boosted(const typename RecT<S>::raw &r,
                                                         const RayView &v, bool beaming) {
+#pragma clang fp contract(off)
     typename RecT<S>::val j;
     const typename RecT<S>::val f = boost_factor<S>(r, v, beaming, j);
     return j * f;
@@ -633,6 +637,20 @@ __device__ __forceinline__ void kahan_add(A &sum, A &comp, A term, bool kahan) {
     }
 }
 
+// The epoch interpolation a + w (b - a) of a sample's two values, as one fma
+// after the difference, in every path alike.
+__device__ __forceinline__ float lerp_w(float a, float b, float w) {
+#pragma clang fp contract(off)
+    return fmaf(w, b - a, a);
+}
+__device__ __forceinline__ double lerp_w(double a, double b, double w) {
+#pragma clang fp contract(off)
+    return fma(w, b - a, a);
+}
+// The same with the difference given (the emissivity plane's FP16 difference
+// is one mixed-precision fma).
+__device__ __forceinline__ float lerp_d(float a, float d, float w) { return fmaf(w, d, a); }
+
 // Cells walked per batch (K): a lane walks K cells of its ray, then issues all
 // their record loads back to back, then consumes them.  The batched kernel
 // comes with K = 4 and K = 8 (a tuning choice); the plain kernel uses 4.
@@ -926,22 +944,39 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
             if (!__any(jplane_mark<S>(any_bits) != 0u)) {
 #pragma unroll
                 for (int k = 0; k < K; k++) {
-                    const A val =
-                        (A)decode_j<S>((JF)q0[k]) + cw[k] * plane_diff<S>(q0[k], q1[k]);
+                    const A val = lerp_d((A)decode_j<S>((JF)q0[k]), plane_diff<S>(q0[k], q1[k]), cw[k]);
                     const A term = cds[k] * val;
                     kahan_add(sum, comp, term, kahan);
                 }
                 continue;
             }
-            // the same cells' whole records, then the record path
+            // Whole records only of the marked elements.  An element without
+            // the mark is its record's j (>= 0, at rest), whose Doppler factor
+            // is exactly 1, so every sample below has the value the record
+            // path gives it, bit for bit, and only the lanes and cells that
+            // need a record load it.
+            bool mk0[K], mk1[K];
 #pragma unroll
             for (int k = 0; k < K; k++) {
+                mk0[k] = jplane_mark<S>(jplane_bits<S>((JF)q0[k])) != 0u;
+                mk1[k] = jplane_mark<S>(jplane_bits<S>((JF)q1[k])) != 0u;
                 GRaw *ra;
                 if constexpr (O32) ra = gdata + (addr[k] >> ESH);
                 else ra = gdata + (addr[k] - wdata);
-                r0[k] = load_grec<S>(ra);
-                r1[k] = load_grec<S>(ra + second);
+                r0[k] = Raw{};
+                r1[k] = Raw{};
+                if (mk0[k]) r0[k] = load_grec<S>(ra);
+                if (mk1[k]) r1[k] = load_grec<S>(ra + second);
             }
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const A b0 = mk0[k] ? (A)boosted<S>(r0[k], v, beaming) : (A)decode_j<S>((JF)q0[k]);
+                const A b1 = mk1[k] ? (A)boosted<S>(r1[k], v, beaming) : (A)decode_j<S>((JF)q1[k]);
+                const A val = lerp_w(b0, b1, cw[k]);
+                const A term = cds[k] * val;
+                kahan_add(sum, comp, term, kahan);
+            }
+            continue;
         } else {
 #pragma unroll
             for (int k = 0; k < K; k++) {
@@ -985,9 +1020,7 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
         if (!VEC && at_rest) {
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                A val = (A)record_j<S>(r0[k]);
-                const A b1 = (A)record_j<S>(r1[k]);
-                val = val + cw[k] * (b1 - val);
+                const A val = lerp_w((A)record_j<S>(r0[k]), (A)record_j<S>(r1[k]), cw[k]);
                 const A term = cds[k] * val;
                 kahan_add(sum, comp, term, kahan);
             }
@@ -1007,14 +1040,14 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
                 val = (A)boosted<S>(r0[k], v, beaming);
                 b1 = (A)boosted<S>(r1[k], v, beaming);
             }
-            val = val + cw[k] * (b1 - val);
+            val = lerp_w(val, b1, cw[k]);
             if constexpr (VEC) {
 #pragma unroll
                 for (int c = 0; c < NX; c++) {
                     if (c < nx) {
                         A xv = (A)(decode_j<S>(j0[k][c]) * f0);
                         const A xb = (A)(decode_j<S>(j1[k][c]) * f1);
-                        xv = xv + cw[k] * (xb - xv);
+                        xv = lerp_w(xv, xb, cw[k]);
                         const A xt = cds[k] * xv;
                         kahan_add(xsum[c], xcomp[c], xt, kahan);
                     }
