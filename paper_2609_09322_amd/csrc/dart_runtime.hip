@@ -1328,7 +1328,12 @@ hipError_t dart::enqueue_plan(const std::vector<Group> &groups, int32_t n,
                                         (g.labelled ? KV_LABELLED : 0) | (g.exact ? KV_EXACT : 0) |
                                         (g.jp ? KV_JP : 0) | (g.jp32 ? KV_JP32 : 0) |
                                         (tun.cells_per_batch == 8 ? KV_K8 : 0);
-        e = launch_batch(g.store, g.f64, variant, bl, blocks, stream);
+        // no more wavefronts than queued tiles: a small batch (one served
+        // request of a few hundred tiles) launches only the workgroups its
+        // tiles keep busy, instead of a full grid whose idle waves each visit
+        // every queue head
+        const int grid = std::max(1, std::min(blocks, (int)((bl.n_tiles + 3) / 4)));
+        e = launch_batch(g.store, g.f64, variant, bl, grid, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
