@@ -145,9 +145,9 @@ dart_status dart_free_epochs(dart_stack *s);
  * after its records change (not inside a stream capture, and by
  * dart_render_batch_noalloc only into a plane already allocated).  The value's
  * sign bit marks records that must be read whole: any velocity bit set, or a
- * negative (or -0) emissivity.  A render reads the plane, and the whole records
- * only of the batches of cells where a record carries the mark; a
- * jet's volume at rest is then read at a quarter of the bytes.  Images, flux
+ * negative (or -0) emissivity.  A render reads the plane, and whole records
+ * only of the marked elements; a jet's volume at rest is then read at a
+ * quarter of the bytes.  Images, flux
  * and cell-steps are bit for bit those of whole-record reads
  * (DART_RECORDS_ONLY).  Without room for the plane (hipMalloc fails) renders
  * read whole records, as do views with DART_NO_KAHAN.  Planes of at most 4 GiB
