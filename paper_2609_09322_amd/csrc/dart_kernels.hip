@@ -919,11 +919,11 @@ __device__ __forceinline__ double march_walk(const RayView &v, const StackDev &s
             // Emissivity elements first.  When no element of the batch, on
             // any lane, carries the read-whole mark, every record it reads is
             // at rest with j >= 0 and the element is its j: the batch is
-            // consumed from the elements with the arithmetic of the at-rest
-            // path below, and its sums are bit for bit those of the records.
+            // consumed from the elements with the arithmetic of the record
+            // path, and its sums are bit for bit those of the records.
             // (Marks on cells that contribute nothing send the batch to the
-            // whole records too, which is never wrong, and saves a test per
-            // cell.)
+            // marked path below too, which is never wrong, and saves a test
+            // per cell.)
             // (16-bit elements held zero-extended, as loaded)
             using QJ = typename std::conditional<sizeof(JF) == 2, uint32_t, JF>::type;
             QJ q0[K], q1[K];
